@@ -1,0 +1,213 @@
+/*
+ * cg.h -- C ABI of the MI355X integral-image cartogram library (libcg.so).
+ *
+ * The library computes contiguous cartograms by the iterative
+ * density-equalising transformation (DET) built on integral images:
+ * every iteration rasterises the region polygons into a density texture
+ * (value over current area, background density = shape parameter times
+ * the mean density), computes the axis-aligned and 45-degree tilted
+ * integral images, moves every vertex by the bilinearly interpolated
+ * eight-anchor displacement and recomputes the region areas
+ * (paper: Method, "Construction of Static Cartograms", Steps 0-7;
+ * Background, eqs. (1)-(3)).
+ *
+ * Conventions shared by every call:
+ *   - Texture side N is a power of two, 16 <= N <= 8192 (Background,
+ *     remark after eq.(1)).  Pixel (p, q) covers [p, p+1] x [q, q+1] in
+ *     pixel units, p = column (x), q = row (y); the y axis points down.
+ *     Node (i, j), 0 <= i, j <= N, sits at (x, y) = (i/N, j/N).
+ *   - Positions are float32 pairs (x, y) in the unit square, array
+ *     [n][2].  Region ids are 1..R; id 0 is the background.
+ *   - Every array argument is DEVICE memory unless its comment says
+ *     host.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the context's own stream).  All
+ *     calls are asynchronous on `stream` unless stated otherwise.
+ *   - Every call returns CG_OK or a negative CG_E* code; invalid
+ *     arguments are rejected before anything is launched, and
+ *     cg_last_error() then describes the problem.  One context per host
+ *     thread; calls on one context must not run concurrently.
+ */
+#ifndef CG_H_
+#define CG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CG_OK 0
+#define CG_EINVAL (-1)
+#define CG_ENOMEM (-2)
+#define CG_EDEVICE (-3)
+#define CG_EUNSUPPORTED (-4)
+
+/* Accumulation precision of the integral images (tables stored as float
+ * for F32/COMP, double for F64). */
+#define CG_F32 0  /* float accumulation */
+#define CG_COMP 1 /* compensated float (TwoSum) accumulation, float carries in double */
+#define CG_F64 2  /* double accumulation and storage */
+
+#define CG_DIRECT 0     /* every time step deforms the original map */
+#define CG_CUMULATIVE 1 /* every time step starts from the previous cartogram */
+
+#define CG_AREA_PIXEL 0   /* density = value / pixel count (Step 2) */
+#define CG_AREA_POLYGON 1 /* density = value / shoelace area */
+
+/* Per-step outcome of the stopping rule (Method, end of the static
+ * construction): max area error below tol, no new minimum within
+ * `patience` iterations, iteration cap, or an internal error. */
+#define CG_STATUS_CONVERGED 0
+#define CG_STATUS_STALLED 1
+#define CG_STATUS_MAXITER 2
+#define CG_STATUS_ERROR 3
+
+/* Flags raised during a run (OR-ed). */
+#define CG_FLAG_CONTESTED 1 /* a pixel centre was claimed by two regions: the map folded */
+#define CG_FLAG_OVERFLOW 2  /* a crossing buffer overflowed: results invalid */
+#define CG_FLAG_FALLBACK 4  /* a warm start was rejected and the plain start used */
+
+typedef struct cg_ctx cg_ctx;
+typedef struct cg_map cg_map;
+
+/* Context: owns a stream, scratch workspaces, the tile-shape table and
+ * the autotune cache.  `device` is the HIP device ordinal. */
+int cg_create(int device, cg_ctx** out);
+int cg_destroy(cg_ctx* ctx);
+/* Text of the last error on this context (never NULL; owned by ctx). */
+const char* cg_last_error(const cg_ctx* ctx);
+/* The context's stream (a hipStream_t). */
+void* cg_stream(const cg_ctx* ctx);
+
+/* Map topology (Method, Step 0: regions given as polygons with shared
+ * boundaries).  Host arrays: rings in CSR form, ring_off [n_rings+1],
+ * ring_idx [ring_off[n_rings]] vertex ids in 0..n_vertices-1 (each ring
+ * listed once, not closed), ring_reg [n_rings] region id in 1..n_regions.
+ * Rings must have positive signed area 0.5*sum(x_k y_{k+1} - x_{k+1} y_k)
+ * (a region may own several rings; holes are not supported).  The call
+ * builds the unique edge table (each edge with the regions on its two
+ * sides, 0 outside the map) and uploads it.  CG_EINVAL when an edge is
+ * used by more than two rings or indices are out of range.  Vertex
+ * positions are not part of the map: they are caller-owned device
+ * arrays.  Blocking (uploads finish before return). */
+int cg_map_build(cg_ctx* ctx, int32_t n_vertices, int32_t n_regions, int32_t n_rings,
+                 const int32_t* ring_off, const int32_t* ring_idx, const int32_t* ring_reg,
+                 cg_map** out);
+int cg_map_destroy(cg_map* map);
+int32_t cg_map_n_edges(const cg_map* map);
+
+/* Step 2 (region area by pixel counting): label map of the map at
+ * positions xy [n_vertices][2].  labels: uint16 [N][N], row = y, value =
+ * region whose polygon contains the pixel centre under the exact rule:
+ * coordinates snapped to X = rint(x*256N), a row is crossed by an edge
+ * when exactly one endpoint has Y <= 256q+128, a centre on an edge
+ * belongs to the region on its +x side; a centre claimed by several
+ * regions (folded map) gets the highest claiming id.  counts: int64
+ * [R+1] pixel counts o(v) (index 0 = background), or NULL.  contested:
+ * int64 [1] number of contested pixels, or NULL. */
+int cg_rasterize(cg_ctx* ctx, const cg_map* map, const float* xy, int N, uint16_t* labels,
+                 int64_t* counts, int64_t* contested, void* stream);
+
+/* Node integral images of one texture (Background, "Integral Images",
+ * eq.(1)).  Element type: float for CG_F32/CG_COMP, double for CG_F64.
+ *   S  [(N+1)][pitch]: S[j][i] = integral of d over [0,i] x [0,j]
+ *   T  [(N+1)][pitch]: integral of d over the top wedge of node (i,j),
+ *                      { (x',y') : y' <= j - |x' - i| }
+ *   HA [2N+1]: HA[s] = integral over x'+y' <= s
+ *   HB [2N+1]: HB[r+N] = integral over y'-x' <= r
+ * All eight integral images of a node are O(1) combinations of these
+ * (alpha = S, beta = S(i,N)-S, delta = S(N,j)-S, gamma = C-S(i,N)-S(N,j)+S,
+ *  alpha_t = T, beta_t = HA-T, delta_t = HB-T, gamma_t = C-HA-HB+T). */
+typedef struct {
+  int32_t N;
+  int32_t precision;
+  int64_t pitch; /* elements per node-table row, >= N+1 */
+  void* S;
+  void* T;
+  void* HA;
+  void* HB;
+} cg_inim;
+
+/* Sizes the caller allocates for cg_integral_image (any argument may be NULL). */
+int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size_t* marginal_bytes);
+
+/* Step 4: integral images of the density texture.  Either labels (uint16
+ * [N][N]) with lut (float [n_lut] density per label; every label must be
+ * < n_lut), or, when `density` is not NULL, a dense float [N][N]
+ * texture (labels/lut ignored).  out->S, T, HA, HB are caller buffers of
+ * cg_inim_size's sizes; out->N/precision/pitch are filled in. */
+int cg_integral_image(cg_ctx* ctx, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
+                      const float* density, int precision, cg_inim* out, void* stream);
+
+/* Steps 5-6: move n_points points by the DET displacement
+ * D = t(.; d) - t(.; d0) of eqs.(2)-(3), evaluated at the four corner
+ * nodes of each point from `inim` and interpolated bilinearly, then
+ * clamped to [0,1]^2.  xy_out may alias xy_in. */
+int cg_map_points(cg_ctx* ctx, const cg_inim* inim, const float* xy_in, float* xy_out,
+                  int64_t n_points, void* stream);
+
+/* Region areas by the shoelace formula and the cartographic errors
+ * (Background, "Quality Measures").  areas: double [R+1]; areas[v] =
+ * sum of v's ring areas, areas[0] = 1 - sum (the background).  When
+ * values (float [R]) and eps_xi (double [2]) are given, eps_xi receives
+ * the mean and max of |A-w|/max(A,w), w(v) = s(v) * sum_u A(u) / sum_u s(u).
+ * Deterministic: fixed-order FP64 reductions, no atomics. */
+int cg_region_areas(cg_ctx* ctx, const cg_map* map, const float* xy, const float* values,
+                    double* areas, double* eps_xi, void* stream);
+
+/* Whole cartograms for time series (Method, Steps 0-7 iterated with the
+ * stopping rule; "Coherence of Dynamic Cartograms" for the direct and
+ * cumulative strategies).  One descriptor per series; every series has
+ * n_steps value vectors.  Direct steps of all series run together in one
+ * batch; cumulative steps run in order, all series together. */
+typedef struct {
+  const cg_map* map;
+  const float* xy0;     /* [n_vertices][2] original map */
+  int32_t N;            /* texture side */
+  int32_t n_steps;      /* T >= 1 */
+  const float* values;  /* [T][R] */
+  int32_t mode;         /* CG_DIRECT / CG_CUMULATIVE */
+  float shape;          /* b: background density = b * d0 (1 = the paper's default) */
+  int32_t area_source;  /* CG_AREA_PIXEL (default) / CG_AREA_POLYGON */
+  float tol;            /* stop when max area error < tol (0.01) */
+  int32_t patience;     /* stop when no new minimum for this many iterations (32) */
+  int32_t max_iters;    /* iteration cap (512) */
+  int32_t fixed_iters;  /* > 0: run exactly this many iterations, no stopping rule */
+  int32_t precision;    /* CG_F32 / CG_COMP / CG_F64 */
+  int32_t frames;       /* K >= 2: K-1 interpolated frames per transition; 0: none */
+  const float* extra;   /* [n_extra][2] tracer points moved along, or NULL */
+  int64_t n_extra;
+  const float* init_field; /* warm start: float [2][G+1][G+1] displacement at grid nodes, or NULL */
+  int32_t init_G;
+} cg_series_desc;
+
+typedef struct {
+  float* xy;        /* device [T][n_vertices][2] */
+  float* extra_xy;  /* device [T][n_extra][2] or NULL */
+  float* frames;    /* device [T-1][K-1][n_vertices][2] or NULL */
+  int32_t* iters;   /* HOST [T] iterations done */
+  int32_t* status;  /* HOST [T] CG_STATUS_* */
+  int32_t* flags;   /* HOST [T] CG_FLAG_* */
+  double* eps;      /* HOST [T] final mean area error */
+  double* xi;       /* HOST [T] final max area error */
+} cg_series_out;
+
+/* Runs every series in desc[0..n_series); out[k] receives series k.
+ * Blocking: returns when all steps have stopped.  Iterations are issued
+ * as captured HIP graphs of `graph_iters` iterations (<= 0: default),
+ * with a convergence poll between replays. */
+int cg_step_series(cg_ctx* ctx, const cg_series_desc* desc, int n_series, cg_series_out* out,
+                   int32_t graph_iters, void* stream);
+
+/* Integral-image tile shape used for (N, batch pixel count); the
+ * autotuner (cg_autotune) fills the table, defaults otherwise.  Both may
+ * be called at any time; cg_autotune times every candidate shape on
+ * synthetic textures (blocking). */
+int cg_tile_shape(const cg_ctx* ctx, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th);
+int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CG_H_ */
