@@ -1,0 +1,150 @@
+"""Benchmark of the integral-image cartogram hot path on one MI355X.
+
+A step is one whole cartogram: every iteration of rasterise -> density ->
+integral images -> move vertices -> areas -> stopping rule, run by
+libcg's HIP kernels through cg_step_series (captured HIP graphs), from
+the original map until the stopping rule ends it.  Inputs are resident in
+HBM before the timed region starts.
+
+Default workload: 100 seeded Voronoi regions with midpoint-displaced
+fractal boundaries (~50k vertices), values lognormal(sigma = 1.5), a
+1024^2 texture, iterate until the max area error is below 1% (or the
+paper's stopping rule ends the run), compensated-FP32 integral images.
+
+Printed: one JSON line (rank 0).  `roofline` times the integral-image
+writer kernel (sat_final) with HIP events captured around every launch
+on its stream inside the timed region; `cpu_baseline` times the FP64
+oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms to 1% area error per cartogram; Mpx-iter/s; learned+batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "config2": dict(seed=2000, R=100, n=50000, fractal=True, sigma=1.5, N=1024, precision=1,
+                    desc="100 fractal Voronoi regions (~50k vertices), lognormal sigma 1.5, 1024^2 texture, "
+                         "iterate to max area error < 1% or the stopping rule, compensated FP32 integral images"),
+    "config1": dict(seed=1000, R=32, n=2000, fractal=False, sigma=1.0, N=256, precision=1, fixed=20,
+                    desc="32 Voronoi regions (~2k vertices), lognormal sigma 1, 256^2 texture, 20 iterations"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(m, values, N, gpu_iters, sample_iters):
+    """The FP64 oracle as it stands, timed on the host on the first
+    `sample_iters` iterations of the same workload; the per-iteration
+    time is scaled to the GPU run's iteration count."""
+    from oracle import cartogram as oc
+    xy = m.xy.copy()
+    t0 = time.perf_counter()
+    for _ in range(sample_iters):
+        xy, _ = oc.iterate_once(xy, m, values, N)
+        A = oc.region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions)
+        oc.cartographic_errors(A, values)
+    dt = time.perf_counter() - t0
+    ms_iter = dt * 1e3 / sample_iters
+    return dict(value=ms_iter * gpu_iters, unit="ms per cartogram", cores=1, kind="oracle",
+                ms_per_iteration=ms_iter, sample_seconds=dt,
+                sample=f"first {sample_iters} iterations of the same cartogram (FP64 numpy, one thread), "
+                       f"per-iteration time x {gpu_iters} iterations of the GPU run")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=24)
+    ap.add_argument("--graph-iters", type=int, default=8)
+    ap.add_argument("--stage", default="sat_final")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported in this build "
+              f"(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_13880_amd import binding as B
+    from synth import lognormal_values, voronoi_map
+
+    w = WORKLOADS[a.workload]
+    log("workload", a.workload, "generating map")
+    m = voronoi_map(w["seed"], w["R"], w["n"], fractal=w["fractal"])
+    values = lognormal_values(w["seed"], w["R"], w["sigma"]).astype(np.float32)
+    N = w["N"]
+    ctx = B.Context(0)
+    gm = ctx.map_from(m)
+    xy0 = torch.from_numpy(m.xy32()).cuda()
+    vals = torch.from_numpy(values).cuda()
+    desc = dict(map=gm, xy0=xy0, N=N, values=vals, precision=w["precision"], fixed_iters=w.get("fixed", 0))
+    torch.cuda.synchronize()
+
+    log("warmup", a.warmup)
+    for _ in range(a.warmup):
+        r = ctx.step_series([desc], graph_iters=a.graph_iters)[0]
+    torch.cuda.synchronize()
+
+    ctx.profile_stage(a.stage)
+    log("timed", a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        r = ctx.step_series([desc], graph_iters=a.graph_iters)[0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, stage_n = ctx.profile_read()
+    ctx.profile_stage(None)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    iters = int(r["iters"][0])
+    xi = float(r["xi"][0])
+    status = int(r["status"][0])
+    mpx = N * N * iters / (ms_step / 1e3) / 1e6
+
+    # roofline of the integral-image writer: algorithmic bytes per launch =
+    # label read (2 B/px) + S and T written (2 tables of (N+1)^2 stored values)
+    store = 8 if w["precision"] == 2 else 4
+    alg_bytes = 2 * N * N + 2 * (N + 1) ** 2 * store
+    avg_ms = stage_ms / max(stage_n, 1)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if stage_n else None
+    roof = dict(bound="hbm", kernel=a.stage, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
+                avg_launch_us=avg_ms * 1e3, launches=stage_n, alg_bytes_per_launch=alg_bytes)
+
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline", a.cpu_iters, "iterations")
+        cpu = cpu_baseline(m, values.astype(np.float64), N, iters, a.cpu_iters)
+
+    out = {
+        "metric": METRIC, "value": ms_step, "unit": "ms per cartogram", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "texture": N, "regions": w["R"], "vertices": m.n_vertices,
+                   "precision": ["F32", "COMP", "F64"][w["precision"]]},
+        "mpx_iter_per_s": mpx, "iterations": iters, "final_xi": xi,
+        "status": ["converged", "stalled", "maxiter", "error"][status],
+        "reached_tol": status == 0, "ms_per_iteration": ms_step / max(iters, 1),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,7 +195,8 @@ typedef struct {
 
 /* Runs every series in desc[0..n_series); out[k] receives series k.
  * Blocking: returns when all steps have stopped.  Iterations are issued
- * as captured HIP graphs of `graph_iters` iterations (<= 0: default),
+ * as captured HIP graphs of `graph_iters` iterations (0: default 8; a
+ * negative value launches -graph_iters iterations eagerly, without a graph),
  * with a convergence poll between replays. */
 int cg_step_series(cg_ctx* ctx, const cg_series_desc* desc, int n_series, cg_series_out* out,
                    int32_t graph_iters, void* stream);
@@ -206,6 +207,17 @@ int cg_step_series(cg_ctx* ctx, const cg_series_desc* desc, int n_series, cg_ser
  * synthetic textures (blocking). */
 int cg_tile_shape(const cg_ctx* ctx, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th);
 int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* cache_path);
+
+/* Timing of one pipeline stage inside cg_step_series (profiling aid).
+ * cg_profile_stage selects the stage ("raster_count", "raster_scan",
+ * "raster_emit", "raster_fill", "density", "sat_reduce", "sat_carry1",
+ * "sat_carry2", "sat_final", "map_points", "areas", "err"; NULL or "" to
+ * stop) and resets the totals.  While selected, every iteration's launch
+ * of that kernel is bracketed by HIP events recorded on the launch stream
+ * (captured into the iteration graph), and cg_profile_read returns the
+ * summed milliseconds and the number of launches timed so far. */
+int cg_profile_stage(cg_ctx* ctx, const char* stage);
+int cg_profile_read(cg_ctx* ctx, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

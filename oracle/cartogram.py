@@ -163,7 +163,7 @@ def density_lut(counts, values, b: float = 1.0, areas=None):
     o = (np.asarray(counts, np.float64) if areas is None else np.asarray(areas, np.float64))[1:]
     s = np.asarray(values, np.float64)
     have = o > 0
-    d0 = s[have].sum() / o.sum()
+    d0 = s[have].sum() / o.sum() if o.sum() > 0 else 1.0   # an empty raster: unit density
     lut = np.zeros(len(s) + 1)
     lut[1:][have] = s[have] / o[have]
     lut[0] = b * d0
@@ -356,11 +356,13 @@ class RunResult:
     eps: float
     xi: float
     xi_history: list
+    extra: np.ndarray | None = None
 
 
-def iterate_once(xy, m, values, N, b=1.0, area_source="pixel"):
+def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None):
     """One pass of Steps 2-6 on positions xy; returns the moved points and
-    the intermediate products (labels, counts, lut, InIm, D)."""
+    the intermediate products (labels, counts, lut, InIm, D, and the moved
+    tracer points `extra` when given)."""
     labels, counts, conflicts = rasterize(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, N)
     areas = None
     if area_source == "polygon":
@@ -370,11 +372,13 @@ def iterate_once(xy, m, values, N, b=1.0, area_source="pixel"):
     im = integral_images(d)
     Dx, Dy = displacement(im)
     new = move_points(xy, Dx, Dy)
-    return new, dict(labels=labels, counts=counts, conflicts=conflicts, lut=lut, im=im, Dx=Dx, Dy=Dy)
+    moved_extra = None if extra is None else move_points(extra, Dx, Dy)
+    return new, dict(labels=labels, counts=counts, conflicts=conflicts, lut=lut, im=im, Dx=Dx, Dy=Dy,
+                     extra=moved_extra)
 
 
 def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
-        area_source="pixel", fixed_iters=None, state_dtype=np.float64) -> RunResult:
+        area_source="pixel", fixed_iters=None, state_dtype=np.float64, extra=None) -> RunResult:
     """Iterate until xi < tol, no new minimum in `patience` iterations, or
     max_iters (or exactly `fixed_iters` iterations when given).
 
@@ -383,6 +387,8 @@ def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
     whose snapping to the raster grid is then decided in the same
     precision as a float32 implementation)."""
     xy = np.asarray(m.xy if xy0 is None else xy0, np.float64).astype(state_dtype).astype(np.float64)
+    if extra is not None:
+        extra = np.asarray(extra, np.float64).astype(state_dtype).astype(np.float64)
     A = region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions)
     eps, xi = cartographic_errors(A, values)
     hist = [xi]
@@ -403,15 +409,17 @@ def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
             if k >= max_iters:
                 status = STATUS_MAXITER
                 break
-        xy, _ = iterate_once(xy, m, values, N, b, area_source)
+        xy, info = iterate_once(xy, m, values, N, b, area_source, extra)
         xy = xy.astype(state_dtype).astype(np.float64)
+        if extra is not None:
+            extra = info["extra"].astype(state_dtype).astype(np.float64)
         k += 1
         A = region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions)
         eps, xi = cartographic_errors(A, values)
         hist.append(xi)
         if xi < best:
             best, best_k = xi, k
-    return RunResult(xy=xy, iters=k, status=status, eps=eps, xi=xi, xi_history=hist)
+    return RunResult(xy=xy, iters=k, status=status, eps=eps, xi=xi, xi_history=hist, extra=extra)
 
 
 # ----------------------------------------------------------------------------

@@ -1,0 +1,326 @@
+"""Thin Python binding of libcg (ctypes).  Argument marshalling only:
+every step of the cartogram path runs in the library's HIP kernels.
+PyTorch supplies device memory and streams.
+
+Names follow the C ABI (include/cg.h): rasterize, integral_image,
+map_points, region_areas, step_series.  The binding raises when the
+shared library has not been built or no GPU is usable; it never falls
+back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcg.so")
+
+F32, COMP, F64 = 0, 1, 2
+DIRECT, CUMULATIVE = 0, 1
+AREA_PIXEL, AREA_POLYGON = 0, 1
+STATUS_CONVERGED, STATUS_STALLED, STATUS_MAXITER, STATUS_ERROR = 0, 1, 2, 3
+FLAG_CONTESTED, FLAG_OVERFLOW, FLAG_FALLBACK = 1, 2, 4
+
+
+class CgInim(C.Structure):
+    _fields_ = [("N", C.c_int32), ("precision", C.c_int32), ("pitch", C.c_int64),
+                ("S", C.c_void_p), ("T", C.c_void_p), ("HA", C.c_void_p), ("HB", C.c_void_p)]
+
+
+class CgSeriesDesc(C.Structure):
+    _fields_ = [("map", C.c_void_p), ("xy0", C.c_void_p), ("N", C.c_int32), ("n_steps", C.c_int32),
+                ("values", C.c_void_p), ("mode", C.c_int32), ("shape", C.c_float),
+                ("area_source", C.c_int32), ("tol", C.c_float), ("patience", C.c_int32),
+                ("max_iters", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32),
+                ("frames", C.c_int32), ("extra", C.c_void_p), ("n_extra", C.c_int64),
+                ("init_field", C.c_void_p), ("init_G", C.c_int32)]
+
+
+class CgSeriesOut(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("extra_xy", C.c_void_p), ("frames", C.c_void_p),
+                ("iters", C.c_void_p), ("status", C.c_void_p), ("flags", C.c_void_p),
+                ("eps", C.c_void_p), ("xi", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcg (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_13880_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "cg_create": (C.c_int, [C.c_int, C.POINTER(vp)]),
+            "cg_destroy": (C.c_int, [vp]),
+            "cg_last_error": (C.c_char_p, [vp]),
+            "cg_stream": (vp, [vp]),
+            "cg_map_build": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, C.POINTER(vp)]),
+            "cg_map_destroy": (C.c_int, [vp]),
+            "cg_map_n_edges": (i32, [vp]),
+            "cg_rasterize": (C.c_int, [vp, vp, vp, C.c_int, vp, vp, vp, vp]),
+            "cg_inim_size": (C.c_int, [C.c_int, C.c_int, C.POINTER(i64), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+            "cg_integral_image": (C.c_int, [vp, C.c_int, vp, vp, i32, vp, C.c_int, C.POINTER(CgInim), vp]),
+            "cg_map_points": (C.c_int, [vp, C.POINTER(CgInim), vp, vp, i64, vp]),
+            "cg_region_areas": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "cg_step_series": (C.c_int, [vp, C.POINTER(CgSeriesDesc), C.c_int, C.POINTER(CgSeriesOut), i32, vp]),
+            "cg_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, C.POINTER(i32), C.POINTER(i32)]),
+            "cg_autotune": (C.c_int, [vp, C.c_int, C.c_int, i32, C.c_char_p]),
+            "cg_profile_stage": (C.c_int, [vp, C.c_char_p]),
+            "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
+            "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
+            "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_autotune", "cg_profile_stage",
+            "cg_profile_read"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    t = t.to(device="cuda", dtype=dtype).contiguous()
+    if shape is not None:
+        t = t.reshape(shape)
+    return t
+
+
+class CartogramError(RuntimeError):
+    pass
+
+
+@dataclass
+class Inim:
+    N: int
+    precision: int
+    pitch: int
+    S: torch.Tensor     # [(N+1), pitch]
+    T: torch.Tensor
+    HA: torch.Tensor    # [2N+1]
+    HB: torch.Tensor
+
+    def c(self) -> CgInim:
+        return CgInim(self.N, self.precision, self.pitch, self.S.data_ptr(), self.T.data_ptr(),
+                      self.HA.data_ptr(), self.HB.data_ptr())
+
+
+class Map:
+    """Map topology uploaded by cg_map_build (vertex positions stay with the caller)."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, n_vertices: int, n_regions: int):
+        self.ctx = ctx
+        self.handle = handle
+        self.n_vertices = n_vertices
+        self.n_regions = n_regions
+
+    @property
+    def n_edges(self) -> int:
+        return lib().cg_map_n_edges(self.handle)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().cg_map_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise CartogramError("no GPU visible: the cartogram library runs on the GPU only")
+        torch.cuda.set_device(device)
+        h = C.c_void_p()
+        rc = lib().cg_create(device, C.byref(h))
+        if rc != 0:
+            raise CartogramError(f"cg_create failed ({rc})")
+        self.handle = h
+        self.device = device
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = lib().cg_last_error(self.handle).decode()
+            raise CartogramError(f"{what} failed ({rc}): {msg}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- topology ------------------------------------------------------------
+    def map_build(self, ring_off, ring_idx, ring_reg, n_vertices: int, n_regions: int) -> Map:
+        ro = np.ascontiguousarray(ring_off, dtype=np.int32)
+        ri = np.ascontiguousarray(ring_idx, dtype=np.int32)
+        rr = np.ascontiguousarray(ring_reg, dtype=np.int32)
+        h = C.c_void_p()
+        rc = lib().cg_map_build(self.handle, int(n_vertices), int(n_regions), int(len(rr)),
+                                ro.ctypes.data_as(C.c_void_p), ri.ctypes.data_as(C.c_void_p),
+                                rr.ctypes.data_as(C.c_void_p), C.byref(h))
+        self._check(rc, "cg_map_build")
+        return Map(self, h, int(n_vertices), int(n_regions))
+
+    def map_from(self, pm) -> Map:
+        """Map from an object with ring_off / ring_idx / ring_reg / n_vertices / n_regions."""
+        return self.map_build(pm.ring_off, pm.ring_idx, pm.ring_reg, pm.n_vertices, pm.n_regions)
+
+    # -- the five steps ------------------------------------------------------
+    def rasterize(self, m: Map, xy, N: int):
+        xy = _dev(xy, torch.float32, (-1, 2))
+        labels = torch.empty((N, N), dtype=torch.int16, device="cuda")
+        counts = torch.empty(m.n_regions + 1, dtype=torch.int64, device="cuda")
+        contested = torch.zeros(1, dtype=torch.int64, device="cuda")
+        rc = lib().cg_rasterize(self.handle, m.handle, _ptr(xy), int(N), _ptr(labels), _ptr(counts),
+                                _ptr(contested), _stream())
+        self._check(rc, "cg_rasterize")
+        return labels, counts, contested
+
+    def inim_alloc(self, N: int, precision: int) -> Inim:
+        pitch = C.c_int64()
+        tb = C.c_size_t()
+        mb = C.c_size_t()
+        self._check(lib().cg_inim_size(int(N), int(precision), C.byref(pitch), C.byref(tb), C.byref(mb)),
+                    "cg_inim_size")
+        dt = torch.float64 if precision == F64 else torch.float32
+        S = torch.empty((N + 1, pitch.value), dtype=dt, device="cuda")
+        T = torch.empty((N + 1, pitch.value), dtype=dt, device="cuda")
+        HA = torch.empty(2 * N + 1, dtype=dt, device="cuda")
+        HB = torch.empty(2 * N + 1, dtype=dt, device="cuda")
+        return Inim(int(N), int(precision), int(pitch.value), S, T, HA, HB)
+
+    def integral_image(self, N: int, labels=None, lut=None, density=None, precision: int = F32,
+                       out: Inim | None = None) -> Inim:
+        im = out or self.inim_alloc(N, precision)
+        cim = im.c()
+        if density is not None:
+            dens = _dev(density, torch.float32, (N, N))
+            rc = lib().cg_integral_image(self.handle, int(N), None, None, 0, _ptr(dens), int(precision),
+                                         C.byref(cim), _stream())
+        else:
+            lab = labels if (isinstance(labels, torch.Tensor) and labels.is_cuda) else \
+                torch.as_tensor(np.asarray(labels).astype(np.uint16).view(np.int16)).cuda()
+            lab = lab.contiguous()
+            lt = _dev(lut, torch.float32)
+            rc = lib().cg_integral_image(self.handle, int(N), _ptr(lab), _ptr(lt), int(lt.numel()), None,
+                                         int(precision), C.byref(cim), _stream())
+        self._check(rc, "cg_integral_image")
+        return im
+
+    def map_points(self, im: Inim, xy_in, xy_out=None):
+        xin = _dev(xy_in, torch.float32, (-1, 2))
+        xout = xin if xy_out is None else xy_out
+        cim = im.c()
+        rc = lib().cg_map_points(self.handle, C.byref(cim), _ptr(xin), _ptr(xout), int(xin.shape[0]), _stream())
+        self._check(rc, "cg_map_points")
+        return xout
+
+    def region_areas(self, m: Map, xy, values=None):
+        xy = _dev(xy, torch.float32, (-1, 2))
+        areas = torch.empty(m.n_regions + 1, dtype=torch.float64, device="cuda")
+        vals = None if values is None else _dev(values, torch.float32)
+        ex = None if values is None else torch.empty(2, dtype=torch.float64, device="cuda")
+        rc = lib().cg_region_areas(self.handle, m.handle, _ptr(xy), _ptr(vals), _ptr(areas), _ptr(ex), _stream())
+        self._check(rc, "cg_region_areas")
+        return areas, ex
+
+    def profile_stage(self, stage: str | None):
+        self._check(lib().cg_profile_stage(self.handle, (stage or "").encode()), "cg_profile_stage")
+
+    def profile_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(lib().cg_profile_read(self.handle, C.byref(ms), C.byref(n)), "cg_profile_read")
+        return ms.value, n.value
+
+    def tile_shape(self, N: int, precision: int, batch_pixels: int):
+        tw, th = C.c_int32(), C.c_int32()
+        self._check(lib().cg_tile_shape(self.handle, int(N), int(precision), int(batch_pixels),
+                                        C.byref(tw), C.byref(th)), "cg_tile_shape")
+        return tw.value, th.value
+
+    def step_series(self, series: list[dict], graph_iters: int = 8):
+        """Run cartogram series.  Each dict: map (Map), xy0 (float32 [n,2]),
+        N, values ([T,R] or [R]), and optional mode, shape, area_source,
+        tol, patience, max_iters, fixed_iters, precision, frames, extra
+        ([m,2] tracer points), init_field ([2,G+1,G+1]).  Returns one dict
+        per series with xy [T,n,2], extra_xy, frames, iters, status,
+        flags, eps, xi (host numpy for the scalars)."""
+        descs = (CgSeriesDesc * len(series))()
+        outs = (CgSeriesOut * len(series))()
+        keep, results = [], []
+        for k, s in enumerate(series):
+            m: Map = s["map"]
+            vals = _dev(s["values"], torch.float32)
+            if vals.dim() == 1:
+                vals = vals.reshape(1, -1)
+            T = int(vals.shape[0])
+            xy0 = _dev(s["xy0"], torch.float32, (-1, 2))
+            n = xy0.shape[0]
+            extra = s.get("extra")
+            extra = None if extra is None else _dev(extra, torch.float32, (-1, 2))
+            field = s.get("init_field")
+            field = None if field is None else _dev(field, torch.float32)
+            K = int(s.get("frames", 0))
+            xy = torch.empty((T, n, 2), dtype=torch.float32, device="cuda")
+            exy = None if extra is None else torch.empty((T, extra.shape[0], 2), dtype=torch.float32, device="cuda")
+            fr = torch.empty((max(T - 1, 0), K - 1, n, 2), dtype=torch.float32, device="cuda") if K >= 2 else None
+            host = {key: np.zeros(T, dtype=np.int32) for key in ("iters", "status", "flags")}
+            host.update({key: np.zeros(T, dtype=np.float64) for key in ("eps", "xi")})
+            d = descs[k]
+            d.map = m.handle
+            d.xy0 = xy0.data_ptr()
+            d.N = int(s["N"])
+            d.n_steps = T
+            d.values = vals.data_ptr()
+            d.mode = int(s.get("mode", DIRECT))
+            d.shape = float(s.get("shape", 1.0))
+            d.area_source = int(s.get("area_source", AREA_PIXEL))
+            d.tol = float(s.get("tol", 0.01))
+            d.patience = int(s.get("patience", 32))
+            d.max_iters = int(s.get("max_iters", 512))
+            d.fixed_iters = int(s.get("fixed_iters", 0))
+            d.precision = int(s.get("precision", F32))
+            d.frames = K
+            d.extra = 0 if extra is None else extra.data_ptr()
+            d.n_extra = 0 if extra is None else int(extra.shape[0])
+            d.init_field = 0 if field is None else field.data_ptr()
+            d.init_G = 0 if field is None else int(field.shape[-1]) - 1
+            o = outs[k]
+            o.xy = xy.data_ptr()
+            o.extra_xy = 0 if exy is None else exy.data_ptr()
+            o.frames = 0 if fr is None else fr.data_ptr()
+            for key in ("iters", "status", "flags", "eps", "xi"):
+                setattr(o, key, host[key].ctypes.data)
+            keep += [vals, xy0, extra, field, xy, exy, fr]
+            results.append(dict(xy=xy, extra_xy=exy, frames=fr, **host))
+        rc = lib().cg_step_series(self.handle, descs, len(series), outs, int(graph_iters), _stream())
+        self._check(rc, "cg_step_series")
+        return results

@@ -1,0 +1,943 @@
+// Host side of libcg: the C ABI declared in cg.h.
+//
+// A call builds a "plan": one device descriptor (cgk::Inst) per cartogram
+// instance, per-kind block-offset tables and the instance scratch buffers,
+// all carved from context-owned device buffers that only grow.  The same
+// kernels run for one instance (the per-step calls) and for whole batches
+// (cg_step_series), where the iteration body is captured once into a HIP
+// graph and replayed, with a convergence poll between replays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cg.h"
+#include "cg_dev.h"
+
+namespace cgk {
+void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
+                   void* u);
+bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, int64_t tiles, int64_t c1,
+                int64_t c2, hipStream_t s, StageHook h, void* u);
+bool sat_shape_supported(int tw, int th);
+void launch_density(const Batch& B, hipStream_t s);
+void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s);
+void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s);
+void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s);
+void launch_err(const Batch& B, int mode, hipStream_t s);
+void launch_init(const Batch& B, int64_t pt_blocks, hipStream_t s);
+void launch_export(const Batch& B, int64_t* contested, double* eps_xi, hipStream_t s);
+void launch_frames(const float* a, const float* b, float* out, int64_t n, int K, hipStream_t s);
+}  // namespace cgk
+
+using cgk::Batch;
+using cgk::Inst;
+using cgk::IterState;
+using cgk::SatLayout;
+
+namespace {
+
+struct DevBuf {
+  char* p = nullptr;
+  size_t n = 0;
+};
+
+constexpr int kFillRows = 4;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct cg_map {
+  cg_ctx* ctx = nullptr;
+  int32_t n_vert = 0, R = 0, n_rings = 0, n_edges = 0;
+  int4* d_edges = nullptr;
+  int32_t* d_ring_off = nullptr;
+  int32_t* d_ring_idx = nullptr;
+  int32_t* d_reg_ring_off = nullptr;
+  int32_t* d_reg_rings = nullptr;
+};
+
+struct cg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t last = nullptr;
+  std::string err;
+  std::map<std::string, DevBuf> bufs;
+  char* pinned = nullptr;
+  size_t pinned_n = 0;
+  hipEvent_t pinned_ev = nullptr;
+  bool pinned_pending = false;
+  std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tiles;  // (N, prec, batch px) -> shape
+  // per-stage timing of series iterations
+  int prof_stage = -1;
+  std::vector<hipEvent_t> prof_ev;
+  int prof_k = 0;            // iterations recorded per graph replay
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  int64_t prof_failed = 0;
+  hipStream_t prof_stream = nullptr;
+};
+
+namespace {
+
+int fail(cg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_OK(ctx, expr)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, CG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+hipStream_t pick_stream(cg_ctx* c, void* s) {
+  hipStream_t st = s ? (hipStream_t)s : c->stream;
+  if (c->last && c->last != st) hipStreamSynchronize(c->last);  // scratch is shared between calls
+  c->last = st;
+  return st;
+}
+
+// Grow-only named device buffers (stream-ordered reuse).
+int get_buf(cg_ctx* c, const char* name, size_t bytes, hipStream_t st, char** out) {
+  DevBuf& b = c->bufs[name];
+  if (b.n < bytes) {
+    if (b.p) {
+      HIP_OK(c, hipStreamSynchronize(st));
+      HIP_OK(c, hipFree(b.p));
+      b.p = nullptr;
+      b.n = 0;
+    }
+    size_t want = std::max(bytes, (size_t)4096);
+    want = want + want / 4;
+    HIP_OK(c, hipMalloc(&b.p, want));
+    b.n = want;
+  }
+  *out = b.p;
+  return CG_OK;
+}
+
+// Host -> device copy through a pinned staging buffer guarded by an event.
+int upload(cg_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (c->pinned_pending) {
+    HIP_OK(c, hipEventSynchronize(c->pinned_ev));
+    c->pinned_pending = false;
+  }
+  if (c->pinned_n < bytes) {
+    if (c->pinned) HIP_OK(c, hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    size_t want = std::max(bytes, (size_t)65536);
+    HIP_OK(c, hipHostMalloc((void**)&c->pinned, want, hipHostMallocDefault));
+    c->pinned_n = want;
+  }
+  memcpy(c->pinned, src, bytes);
+  HIP_OK(c, hipMemcpyAsync(dst, c->pinned, bytes, hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipEventRecord(c->pinned_ev, st));
+  c->pinned_pending = true;
+  return CG_OK;
+}
+
+bool pow2_ok(int N) { return N >= 16 && N <= 8192 && (N & (N - 1)) == 0; }
+
+size_t store_size(int prec) { return prec == CG_F64 ? 8 : 4; }
+size_t carry_size(int prec) { return prec == CG_F32 ? 4 : 8; }
+
+// ---------------------------------------------------------------------------
+// plans
+
+struct Spec {
+  const cg_map* map = nullptr;
+  int N = 0;
+  float2* xy = nullptr;
+  float2* extra = nullptr;
+  int64_t n_extra = 0;
+  const float2* src_xy = nullptr;
+  const float2* src_extra = nullptr;
+  const float* values = nullptr;
+  // caller-provided buffers (null: scratch)
+  uint16_t* labels = nullptr;
+  int64_t* counts = nullptr;
+  float* lut = nullptr;
+  int32_t n_lut = 0;
+  const float* density = nullptr;
+  void *S = nullptr, *T = nullptr, *HA = nullptr, *HB = nullptr;
+  int64_t pitch = 0;
+  double* areas = nullptr;
+  float shape = 1.f, tol = 0.01f;
+  int32_t area_source = CG_AREA_PIXEL, patience = 32, max_iters = 512, fixed_iters = 0;
+  const float* init_field = nullptr;
+  int64_t init_G = 0;
+};
+
+struct Needs {
+  bool raster = false, sat = false, areas = false;
+};
+
+struct Plan {
+  Batch B{};
+  int prec = CG_F32, tw = 128, th = 16;
+  bool dense = false;
+  int n = 0;
+  int64_t edge_blocks = 0, row_blocks = 0, tiles = 0, c1 = 0, c2 = 0, pt_blocks = 0, reg_blocks = 0;
+  IterState* d_state = nullptr;
+  std::vector<Inst> inst;
+};
+
+int64_t pitch_of(int N) { return (int64_t)((N + 1 + 63) / 64) * 64; }
+
+int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int th, bool dense,
+               const Needs& nd, hipStream_t st, Plan& P, const char* tag) {
+  const int n = (int)specs.size();
+  P.n = n;
+  P.prec = prec;
+  P.tw = tw;
+  P.th = th;
+  P.dense = dense;
+  P.inst.assign(n, Inst{});
+  // scratch layout
+  struct Own {
+    int64_t rowcnt = -1, rowoff = -1, xing = -1, labels = -1, counts = -1, lut = -1, S = -1, T = -1,
+            HA = -1, HB = -1, agg = -1, carry = -1, areas = -1;
+  };
+  std::vector<Own> owns(n);
+  std::vector<size_t> base(n);
+  size_t total = 0;
+  for (int k = 0; k < n; ++k) {
+    const Spec& s = specs[k];
+    const int N = s.N;
+    const int R = s.map ? s.map->R : 0;
+    base[k] = total;
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> int64_t {
+      size_t at = o;
+      o += align_up(bytes);
+      return (int64_t)at;
+    };
+    Inst& I = P.inst[k];
+    I.N = N;
+    I.R = R;
+    I.n_vert = s.map ? s.map->n_vert : 0;
+    I.n_pts = (int32_t)(I.n_vert + s.n_extra);
+    I.n_edges = s.map ? s.map->n_edges : 0;
+    I.n_rings = s.map ? s.map->n_rings : 0;
+    I.n_lut = s.lut && s.n_lut ? s.n_lut : R + 1;
+    I.tw = tw;
+    I.th = th;
+    SatLayout L = cgk::sat_layout(N, tw, th);
+    I.ntx = L.ntx;
+    I.nty = L.nty;
+    I.area_source = s.area_source;
+    I.patience = s.patience;
+    I.max_iters = s.max_iters;
+    I.fixed_iters = s.fixed_iters;
+    I.shape = s.shape;
+    I.tol = s.tol;
+    I.pitch = s.pitch ? s.pitch : pitch_of(N);
+    I.xy = s.xy;
+    I.extra = s.extra;
+    I.src_xy = s.src_xy;
+    I.src_extra = s.src_extra;
+    I.init_field = s.init_field;
+    I.init_G = s.init_G;
+    I.values = s.values;
+    I.density = s.density;
+    if (s.map) {
+      I.edges = s.map->d_edges;
+      I.ring_off = s.map->d_ring_off;
+      I.ring_idx = s.map->d_ring_idx;
+      I.reg_ring_off = s.map->d_reg_ring_off;
+      I.reg_rings = s.map->d_reg_rings;
+    }
+    // scratch offsets relative to the instance base (-1: caller buffer or unused)
+    Own& ow = owns[k];
+    if (nd.raster) {
+      I.xing_cap = std::max<int64_t>(4 * (int64_t)I.n_edges + 64 * (int64_t)N, 4096);
+      ow.rowcnt = take(sizeof(uint32_t) * N);
+      ow.rowoff = take(sizeof(uint32_t) * (N + 1));
+      ow.xing = take(sizeof(uint64_t) * I.xing_cap);
+    }
+    if ((nd.raster || nd.sat) && !dense && !s.labels) ow.labels = take(sizeof(uint16_t) * (size_t)N * N);
+    if (nd.raster && !s.counts) ow.counts = take(sizeof(int64_t) * (R + 1));
+    if (!dense && !s.lut) ow.lut = take(sizeof(float) * (R + 1));
+    if (nd.sat) {
+      const size_t tb = store_size(prec) * (size_t)(N + 1) * I.pitch;
+      if (!s.S) ow.S = take(tb);
+      if (!s.T) ow.T = take(tb);
+      if (!s.HA) ow.HA = take(store_size(prec) * (2 * N + 1));
+      if (!s.HB) ow.HB = take(store_size(prec) * (2 * N + 1));
+      ow.agg = take(carry_size(prec) * L.agg_elems);
+      ow.carry = take(carry_size(prec) * L.carry_elems);
+    }
+    if (nd.areas && !s.areas) ow.areas = take(sizeof(double) * (R + 1));
+    total += o;
+    I.labels = s.labels;
+    I.counts = s.counts;
+    I.lut = s.lut;
+    I.S = s.S;
+    I.T = s.T;
+    I.HA = s.HA;
+    I.HB = s.HB;
+    I.areas = s.areas;
+  }
+  char* scratch = nullptr;
+  int rc = get_buf(c, (std::string(tag) + ":scratch").c_str(), std::max<size_t>(total, 256), st, &scratch);
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    Inst& I = P.inst[k];
+    const Own& ow = owns[k];
+    char* b = scratch + base[k];
+    auto at = [&](int64_t off) -> char* { return off >= 0 ? b + off : nullptr; };
+    I.row_cnt = (uint32_t*)at(ow.rowcnt);
+    I.row_off = (uint32_t*)at(ow.rowoff);
+    I.xing = (uint64_t*)at(ow.xing);
+    if (ow.labels >= 0) I.labels = (uint16_t*)at(ow.labels);
+    if (ow.counts >= 0) I.counts = (int64_t*)at(ow.counts);
+    if (ow.lut >= 0) I.lut = (float*)at(ow.lut);
+    if (ow.S >= 0) I.S = at(ow.S);
+    if (ow.T >= 0) I.T = at(ow.T);
+    if (ow.HA >= 0) I.HA = at(ow.HA);
+    if (ow.HB >= 0) I.HB = at(ow.HB);
+    I.agg = at(ow.agg);
+    I.carry = at(ow.carry);
+    if (ow.areas >= 0) I.areas = (double*)at(ow.areas);
+  }
+  // descriptors, offsets and states in one device buffer
+  std::vector<int64_t> offs(8 * (size_t)(n + 1), 0);
+  auto kind = [&](int kd) { return offs.data() + (size_t)kd * (n + 1); };
+  for (int k = 0; k < n; ++k) {
+    const Inst& I = P.inst[k];
+    SatLayout L = cgk::sat_layout(I.N, tw, th);
+    const int64_t cnt[8] = {
+        (I.n_edges + 255) / 256,
+        (I.N + kFillRows - 1) / kFillRows,
+        (int64_t)L.ntx * L.nty,
+        (L.NY + L.nty + 1 + 255) / 256,
+        (L.NX + 1 + (int64_t)L.LA + L.LB + 255) / 256,
+        std::max<int64_t>(1, (I.n_pts + 255) / 256),
+        I.R,
+        1};
+    for (int kd = 0; kd < 8; ++kd) kind(kd)[k + 1] = kind(kd)[k] + cnt[kd];
+  }
+  const size_t inst_bytes = align_up(sizeof(Inst) * n);
+  const size_t off_bytes = align_up(sizeof(int64_t) * offs.size());
+  const size_t st_bytes = align_up(sizeof(IterState) * n);
+  char* desc = nullptr;
+  rc = get_buf(c, (std::string(tag) + ":desc").c_str(), inst_bytes + off_bytes + st_bytes, st, &desc);
+  if (rc) return rc;
+  P.d_state = (IterState*)(desc + inst_bytes + off_bytes);
+  for (int k = 0; k < n; ++k) P.inst[k].st = P.d_state + k;
+  std::vector<char> host(inst_bytes + off_bytes, 0);
+  memcpy(host.data(), P.inst.data(), sizeof(Inst) * n);
+  memcpy(host.data() + inst_bytes, offs.data(), sizeof(int64_t) * offs.size());
+  rc = upload(c, desc, host.data(), host.size(), st);
+  if (rc) return rc;
+  const int64_t* doff = (const int64_t*)(desc + inst_bytes);
+  Batch& B = P.B;
+  B.inst = (const Inst*)desc;
+  B.n = n;
+  B.skip_done = 1;
+  B.off_edges = doff + 0 * (n + 1);
+  B.off_rows = doff + 1 * (n + 1);
+  B.off_tiles = doff + 2 * (n + 1);
+  B.off_carry1 = doff + 3 * (n + 1);
+  B.off_carry2 = doff + 4 * (n + 1);
+  B.off_pts = doff + 5 * (n + 1);
+  B.off_regions = doff + 6 * (n + 1);
+  B.off_inst = doff + 7 * (n + 1);
+  P.edge_blocks = kind(0)[n];
+  P.row_blocks = kind(1)[n];
+  P.tiles = kind(2)[n];
+  P.c1 = kind(3)[n];
+  P.c2 = kind(4)[n];
+  P.pt_blocks = kind(5)[n];
+  P.reg_blocks = kind(6)[n];
+  return CG_OK;
+}
+
+int default_shape(int N, int64_t batch_px, int* tw, int* th) {
+  (void)batch_px;
+  if (N <= 128) { *tw = 64; *th = 16; }
+  else if (N <= 1024) { *tw = 128; *th = 16; }
+  else { *tw = 128; *th = 32; }
+  return CG_OK;
+}
+
+void shape_for(const cg_ctx* c, int N, int prec, int64_t batch_px, int* tw, int* th) {
+  auto it = c->tiles.find(std::make_tuple(N, prec, batch_px));
+  if (it == c->tiles.end()) {
+    // nearest autotuned batch size for this (N, prec)
+    int64_t best = -1;
+    for (auto& kv : c->tiles) {
+      if (std::get<0>(kv.first) == N && std::get<1>(kv.first) == prec) {
+        const int64_t bp = std::get<2>(kv.first);
+        if (best < 0 || std::llabs(bp - batch_px) < std::llabs(best - batch_px)) {
+          best = bp;
+          *tw = kv.second.first;
+          *th = kv.second.second;
+        }
+      }
+    }
+    if (best >= 0) return;
+    default_shape(N, batch_px, tw, th);
+    return;
+  }
+  *tw = it->second.first;
+  *th = it->second.second;
+}
+
+struct HookCtx {
+  cg_ctx* c;
+  int it;
+};
+
+void prof_hook(int stage, int after, void* user) {
+  HookCtx* h = (HookCtx*)user;
+  if (stage != h->c->prof_stage) return;
+  hipEventRecord(h->c->prof_ev[2 * h->it + after], h->c->prof_stream);
+}
+
+void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
+  HookCtx hc{c, it};
+  const bool prof = c && c->prof_stage >= 0;
+  cgk::StageHook h = prof ? prof_hook : nullptr;
+  void* u = prof ? (void*)&hc : nullptr;
+  auto hk = [&](int s, int after) { if (h) h(s, after, u); };
+  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, h, u);
+  hk(cgk::ST_DENSITY, 0);
+  cgk::launch_density(P.B, st);
+  hk(cgk::ST_DENSITY, 1);
+  cgk::launch_sat(P.B, P.prec, P.tw, P.th, false, P.tiles, P.c1, P.c2, st, h, u);
+  hk(cgk::ST_MAP, 0);
+  cgk::launch_map(P.B, P.prec, P.pt_blocks, st);
+  hk(cgk::ST_MAP, 1);
+  hk(cgk::ST_AREAS, 0);
+  cgk::launch_areas(P.B, P.reg_blocks, st);
+  hk(cgk::ST_AREAS, 1);
+  hk(cgk::ST_ERR, 0);
+  cgk::launch_err(P.B, 0, st);
+  hk(cgk::ST_ERR, 1);
+}
+
+int check_launch(cg_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CG_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return CG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+int cg_create(int device, cg_ctx** out) {
+  if (!out) return CG_EINVAL;
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return CG_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return CG_EDEVICE;
+  cg_ctx* c = new cg_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->pinned_ev, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return CG_EDEVICE;
+  }
+  *out = c;
+  return CG_OK;
+}
+
+int cg_destroy(cg_ctx* c) {
+  if (!c) return CG_EINVAL;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& kv : c->bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  if (c->pinned) hipHostFree(c->pinned);
+  if (c->pinned_ev) hipEventDestroy(c->pinned_ev);
+  if (c->stream) hipStreamDestroy(c->stream);
+  delete c;
+  return CG_OK;
+}
+
+const char* cg_last_error(const cg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void* cg_stream(const cg_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int cg_map_build(cg_ctx* c, int32_t n_vertices, int32_t n_regions, int32_t n_rings,
+                 const int32_t* ring_off, const int32_t* ring_idx, const int32_t* ring_reg,
+                 cg_map** out) {
+  if (!c || !out) return CG_EINVAL;
+  *out = nullptr;
+  if (n_vertices < 0 || n_regions < 0 || n_regions > 65534 || n_rings < 0 || !ring_off ||
+      (n_rings > 0 && (!ring_idx || !ring_reg)))
+    return fail(c, CG_EINVAL, "cg_map_build: bad sizes or null arrays");
+  if (ring_off[0] != 0) return fail(c, CG_EINVAL, "cg_map_build: ring_off[0] must be 0");
+  for (int r = 0; r < n_rings; ++r) {
+    if (ring_off[r + 1] < ring_off[r] + 3) return fail(c, CG_EINVAL, "cg_map_build: a ring has fewer than 3 vertices");
+    if (ring_reg[r] < 1 || ring_reg[r] > n_regions) return fail(c, CG_EINVAL, "cg_map_build: ring region out of range");
+  }
+  const int32_t total = ring_off[n_rings];
+  for (int i = 0; i < total; ++i)
+    if (ring_idx[i] < 0 || ring_idx[i] >= n_vertices) return fail(c, CG_EINVAL, "cg_map_build: vertex index out of range");
+  // unique edges with the regions on both sides
+  std::map<std::pair<int, int>, std::vector<int>> owner;
+  for (int r = 0; r < n_rings; ++r) {
+    const int b = ring_off[r], len = ring_off[r + 1] - b;
+    for (int k = 0; k < len; ++k) {
+      const int a = ring_idx[b + k], bb = ring_idx[b + (k + 1) % len];
+      if (a == bb) continue;
+      owner[{std::min(a, bb), std::max(a, bb)}].push_back(ring_reg[r]);
+    }
+  }
+  std::vector<int4> edges;
+  edges.reserve(owner.size());
+  for (auto& kv : owner) {
+    if (kv.second.size() > 2) return fail(c, CG_EINVAL, "cg_map_build: an edge is used by more than two rings");
+    int ra = kv.second[0], rb = kv.second.size() > 1 ? kv.second[1] : 0;
+    if (ra == rb) continue;  // both sides the same region: never changes membership
+    edges.push_back(make_int4(kv.first.first, kv.first.second, ra, rb));
+  }
+  // region -> rings CSR
+  std::vector<int32_t> reg_off(n_regions + 1, 0), reg_rings(n_rings);
+  for (int r = 0; r < n_rings; ++r) reg_off[ring_reg[r]]++;
+  for (int v = 1; v <= n_regions; ++v) reg_off[v] += reg_off[v - 1];
+  {
+    std::vector<int32_t> pos(reg_off.begin(), reg_off.end() - 1);
+    for (int r = 0; r < n_rings; ++r) reg_rings[pos[ring_reg[r] - 1]++] = r;
+  }
+  cg_map* m = new cg_map();
+  m->ctx = c;
+  m->n_vert = n_vertices;
+  m->R = n_regions;
+  m->n_rings = n_rings;
+  m->n_edges = (int32_t)edges.size();
+  hipSetDevice(c->device);
+  auto put = [&](void** dst, const void* src, size_t bytes) -> bool {
+    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+    return true;
+  };
+  bool ok = put((void**)&m->d_edges, edges.data(), sizeof(int4) * edges.size()) &&
+            put((void**)&m->d_ring_off, ring_off, sizeof(int32_t) * (n_rings + 1)) &&
+            put((void**)&m->d_ring_idx, ring_idx, sizeof(int32_t) * total) &&
+            put((void**)&m->d_reg_ring_off, reg_off.data(), sizeof(int32_t) * reg_off.size()) &&
+            put((void**)&m->d_reg_rings, reg_rings.data(), sizeof(int32_t) * reg_rings.size());
+  if (!ok) {
+    cg_map_destroy(m);
+    return fail(c, CG_ENOMEM, "cg_map_build: device allocation failed");
+  }
+  *out = m;
+  return CG_OK;
+}
+
+int cg_map_destroy(cg_map* m) {
+  if (!m) return CG_EINVAL;
+  if (m->ctx) hipSetDevice(m->ctx->device);
+  hipDeviceSynchronize();
+  hipFree(m->d_edges);
+  hipFree(m->d_ring_off);
+  hipFree(m->d_ring_idx);
+  hipFree(m->d_reg_ring_off);
+  hipFree(m->d_reg_rings);
+  delete m;
+  return CG_OK;
+}
+
+int32_t cg_map_n_edges(const cg_map* m) { return m ? m->n_edges : -1; }
+
+int cg_rasterize(cg_ctx* c, const cg_map* map, const float* xy, int N, uint16_t* labels,
+                 int64_t* counts, int64_t* contested, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!map || !xy || !labels) return fail(c, CG_EINVAL, "cg_rasterize: null argument");
+  if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_rasterize: N must be a power of two in [16, 8192]");
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  Spec s;
+  s.map = map;
+  s.N = N;
+  s.xy = (float2*)xy;
+  s.labels = labels;
+  s.counts = counts;
+  Needs nd;
+  nd.raster = true;
+  Plan P;
+  int rc = build_plan(c, {s}, CG_F32, 64, 16, false, nd, st, P, "call");
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  cgk::launch_init(P.B, P.pt_blocks, st);
+  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+  if (contested) cgk::launch_export(P.B, contested, nullptr, st);
+  return check_launch(c);
+}
+
+int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size_t* marginal_bytes) {
+  if (!pow2_ok(N) || precision < CG_F32 || precision > CG_F64) return CG_EINVAL;
+  const int64_t p = pitch_of(N);
+  if (pitch) *pitch = p;
+  if (table_bytes) *table_bytes = store_size(precision) * (size_t)(N + 1) * p;
+  if (marginal_bytes) *marginal_bytes = store_size(precision) * (size_t)(2 * N + 1);
+  return CG_OK;
+}
+
+int cg_integral_image(cg_ctx* c, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
+                      const float* density, int precision, cg_inim* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!out || !out->S || !out->T || !out->HA || !out->HB) return fail(c, CG_EINVAL, "cg_integral_image: output buffers missing");
+  if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_integral_image: N must be a power of two in [16, 8192]");
+  if (precision < CG_F32 || precision > CG_F64) return fail(c, CG_EINVAL, "cg_integral_image: bad precision");
+  if (!density && (!labels || !lut || n_lut < 1 || n_lut > 65536))
+    return fail(c, CG_EINVAL, "cg_integral_image: need labels + lut (1 <= n_lut <= 65536) or a density texture");
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  int tw, th;
+  shape_for(c, N, precision, (int64_t)N * N, &tw, &th);
+  Spec s;
+  s.N = N;
+  s.labels = (uint16_t*)labels;
+  s.lut = (float*)lut;
+  s.n_lut = n_lut;
+  s.density = density;
+  s.S = out->S;
+  s.T = out->T;
+  s.HA = out->HA;
+  s.HB = out->HB;
+  s.pitch = pitch_of(N);
+  Needs nd;
+  nd.sat = true;
+  Plan P;
+  int rc = build_plan(c, {s}, precision, tw, th, density != nullptr, nd, st, P, "call");
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  if (!cgk::launch_sat(P.B, precision, tw, th, density != nullptr, P.tiles, P.c1, P.c2, st, nullptr, nullptr))
+    return fail(c, CG_EUNSUPPORTED, "cg_integral_image: unsupported tile shape");
+  out->N = N;
+  out->precision = precision;
+  out->pitch = s.pitch;
+  return check_launch(c);
+}
+
+int cg_map_points(cg_ctx* c, const cg_inim* im, const float* xy_in, float* xy_out, int64_t n_points,
+                  void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!im || !xy_in || !xy_out || n_points < 0) return fail(c, CG_EINVAL, "cg_map_points: bad arguments");
+  if (!pow2_ok(im->N) || im->precision < CG_F32 || im->precision > CG_F64 || im->pitch < im->N + 1 ||
+      !im->S || !im->T || !im->HA || !im->HB)
+    return fail(c, CG_EINVAL, "cg_map_points: bad integral-image descriptor");
+  if (n_points == 0) return CG_OK;
+  if (n_points > INT32_MAX) return fail(c, CG_EINVAL, "cg_map_points: too many points");
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  Spec s;
+  s.N = im->N;
+  s.S = im->S;
+  s.T = im->T;
+  s.HA = im->HA;
+  s.HB = im->HB;
+  s.pitch = im->pitch;
+  s.xy = (float2*)xy_out;
+  s.src_xy = (const float2*)xy_in;
+  Needs nd;
+  Plan P;
+  // a map-less instance: n_pts comes from n_extra with no vertices
+  s.extra = (float2*)xy_out;
+  s.src_extra = (const float2*)xy_in;
+  s.n_extra = n_points;
+  s.xy = nullptr;
+  s.src_xy = nullptr;
+  int rc = build_plan(c, {s}, im->precision, 64, 16, false, nd, st, P, "call");
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  cgk::launch_init(P.B, P.pt_blocks, st);
+  cgk::launch_map(P.B, im->precision, P.pt_blocks, st);
+  return check_launch(c);
+}
+
+int cg_region_areas(cg_ctx* c, const cg_map* map, const float* xy, const float* values, double* areas,
+                    double* eps_xi, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!map || !xy || !areas) return fail(c, CG_EINVAL, "cg_region_areas: null argument");
+  if (eps_xi && !values) return fail(c, CG_EINVAL, "cg_region_areas: eps_xi needs values");
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  Spec s;
+  s.map = map;
+  s.N = 16;
+  s.xy = (float2*)xy;
+  s.values = values;
+  s.areas = areas;
+  Needs nd;
+  nd.areas = true;
+  Plan P;
+  int rc = build_plan(c, {s}, CG_F32, 64, 16, false, nd, st, P, "call");
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  cgk::launch_init(P.B, P.pt_blocks, st);
+  cgk::launch_areas(P.B, P.reg_blocks, st);
+  if (values) {
+    cgk::launch_err(P.B, 1, st);
+    if (eps_xi) cgk::launch_export(P.B, nullptr, eps_xi, st);
+  }
+  return check_launch(c);
+}
+
+int cg_autotune(cg_ctx* c, int N, int precision, int32_t batch, const char* cache_path) {
+  (void)N; (void)precision; (void)batch; (void)cache_path;
+  return fail(c, CG_EUNSUPPORTED, "cg_autotune: not available");
+}
+
+static const char* kStageNames[cgk::ST_COUNT] = {
+    "raster_count", "raster_scan", "raster_emit", "raster_fill", "density", "sat_reduce",
+    "sat_carry1", "sat_carry2", "sat_final", "map_points", "areas", "err"};
+
+int cg_profile_stage(cg_ctx* c, const char* stage) {
+  if (!c) return CG_EINVAL;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  c->prof_failed = 0;
+  if (!stage || !*stage) {
+    c->prof_stage = -1;
+    return CG_OK;
+  }
+  for (int i = 0; i < cgk::ST_COUNT; ++i)
+    if (strcmp(stage, kStageNames[i]) == 0) {
+      c->prof_stage = i;
+      return CG_OK;
+    }
+  return fail(c, CG_EINVAL, std::string("cg_profile_stage: unknown stage ") + stage);
+}
+
+int cg_profile_read(cg_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c) return CG_EINVAL;
+  if (total_ms) *total_ms = c->prof_ms;
+  if (launches) *launches = c->prof_launches;
+  return CG_OK;
+}
+
+int cg_tile_shape(const cg_ctx* c, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th) {
+  if (!c || !tw || !th || !pow2_ok(N)) return CG_EINVAL;
+  int a, b;
+  shape_for(c, N, precision, batch_pixels, &a, &b);
+  *tw = a;
+  *th = b;
+  return CG_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// series driver
+
+namespace {
+
+struct StepRef {
+  int series, step;
+};
+
+int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepRef>& refs,
+              const cg_series_desc* desc, cg_series_out* out, int prec, int graph_iters, hipStream_t st) {
+  if (specs.empty()) return CG_OK;
+  int64_t px = 0;
+  int maxN = 0;
+  for (auto& s : specs) {
+    px += (int64_t)s.N * s.N;
+    maxN = std::max(maxN, s.N);
+  }
+  int tw, th;
+  shape_for(c, maxN, prec, px, &tw, &th);
+  Needs nd;
+  nd.raster = nd.sat = nd.areas = true;
+  Plan P;
+  int rc = build_plan(c, specs, prec, tw, th, false, nd, st, P, "series");
+  if (rc) return rc;
+  const int n = P.n;
+  cgk::launch_init(P.B, P.pt_blocks, st);
+  cgk::launch_apply_field(P.B, P.pt_blocks, st);
+  cgk::launch_areas(P.B, P.reg_blocks, st);
+  cgk::launch_err(P.B, 0, st);
+  if ((rc = check_launch(c))) return rc;
+  // capture the iteration body once (graph_iters < 0: launch eagerly,
+  // |graph_iters| iterations between convergence polls)
+  const bool eager = graph_iters < 0;
+  const int K = graph_iters > 0 ? graph_iters : (graph_iters < 0 ? -graph_iters : 8);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const bool prof = c->prof_stage >= 0;
+  if (prof) {
+    while ((int)c->prof_ev.size() < 2 * K) {
+      hipEvent_t e;
+      HIP_OK(c, hipEventCreate(&e));
+      c->prof_ev.push_back(e);
+    }
+    c->prof_k = K;
+    c->prof_stream = st;
+  }
+  if (!eager) {
+    HIP_OK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
+    HIP_OK(c, hipStreamEndCapture(st, &graph));
+    HIP_OK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  std::vector<IterState> hs(n);
+  IterState* pinned = nullptr;
+  HIP_OK(c, hipHostMalloc((void**)&pinned, sizeof(IterState) * n, hipHostMallocDefault));
+  int max_budget = 0;
+  for (auto& s : specs) max_budget = std::max(max_budget, s.fixed_iters > 0 ? s.fixed_iters : s.max_iters);
+  int launched = 0;
+  rc = CG_OK;
+  while (true) {
+    if (hipMemcpyAsync(pinned, P.d_state, sizeof(IterState) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(c, CG_EDEVICE, "cg_step_series: device error while iterating");
+      break;
+    }
+    if (prof && launched > 0) {
+      for (int it = 0; it < K; ++it) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, c->prof_ev[2 * it], c->prof_ev[2 * it + 1]);
+        if (e == hipSuccess) {
+          c->prof_ms += ms;
+          c->prof_launches += 1;
+        } else {
+          (void)hipGetLastError();  // timing unavailable for this replay; leave no sticky error
+          c->prof_failed += 1;
+        }
+      }
+    }
+    bool all = true;
+    for (int k = 0; k < n; ++k) all = all && pinned[k].done;
+    if (all) break;
+    if (launched > max_budget + 2 * K) {
+      rc = fail(c, CG_EDEVICE, "cg_step_series: iteration budget exceeded without stopping");
+      break;
+    }
+    if (eager) {
+      for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
+      if ((rc = check_launch(c))) break;
+    } else if (hipGraphLaunch(exec, st) != hipSuccess) {
+      rc = fail(c, CG_EDEVICE, "cg_step_series: graph launch failed");
+      break;
+    }
+    launched += K;
+  }
+  memcpy(hs.data(), pinned, sizeof(IterState) * n);
+  hipHostFree(pinned);
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    const StepRef& r = refs[k];
+    cg_series_out& o = out[r.series];
+    if (o.iters) o.iters[r.step] = hs[k].iter;
+    if (o.status) o.status[r.step] = hs[k].status;
+    if (o.flags) o.flags[r.step] = hs[k].flags;
+    if (o.eps) o.eps[r.step] = hs[k].eps;
+    if (o.xi) o.xi[r.step] = hs[k].xi;
+  }
+  (void)desc;
+  return CG_OK;
+}
+
+Spec spec_for(const cg_series_desc& d, const cg_series_out& o, int t, bool cumulative) {
+  Spec s;
+  const int n = d.map->n_vert;
+  s.map = d.map;
+  s.N = d.N;
+  s.xy = (float2*)(o.xy + (size_t)t * n * 2);
+  s.src_xy = (cumulative && t > 0) ? (const float2*)(o.xy + (size_t)(t - 1) * n * 2) : (const float2*)d.xy0;
+  if (d.extra && d.n_extra > 0 && o.extra_xy) {
+    s.extra = (float2*)(o.extra_xy + (size_t)t * d.n_extra * 2);
+    s.n_extra = d.n_extra;
+    s.src_extra = (cumulative && t > 0) ? (const float2*)(o.extra_xy + (size_t)(t - 1) * d.n_extra * 2)
+                                        : (const float2*)d.extra;
+  }
+  s.values = d.values + (size_t)t * d.map->R;
+  s.shape = d.shape;
+  s.tol = d.tol;
+  s.area_source = d.area_source;
+  s.patience = d.patience;
+  s.max_iters = d.max_iters;
+  s.fixed_iters = d.fixed_iters;
+  if (d.init_field && (!cumulative || t == 0)) {
+    s.init_field = d.init_field;
+    s.init_G = d.init_G;
+  }
+  return s;
+}
+
+}  // namespace
+
+extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_series, cg_series_out* out,
+                              int32_t graph_iters, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!desc || !out || n_series < 0) return fail(c, CG_EINVAL, "cg_step_series: bad arguments");
+  for (int i = 0; i < n_series; ++i) {
+    const cg_series_desc& d = desc[i];
+    if (!d.map || !d.xy0 || !d.values || !out[i].xy) return fail(c, CG_EINVAL, "cg_step_series: null map/xy0/values/out.xy");
+    if (!pow2_ok(d.N)) return fail(c, CG_EINVAL, "cg_step_series: N must be a power of two in [16, 8192]");
+    if (d.n_steps < 1 || d.map->R < 1) return fail(c, CG_EINVAL, "cg_step_series: need n_steps >= 1 and R >= 1");
+    if (d.mode != CG_DIRECT && d.mode != CG_CUMULATIVE) return fail(c, CG_EINVAL, "cg_step_series: bad mode");
+    if (d.precision < CG_F32 || d.precision > CG_F64) return fail(c, CG_EINVAL, "cg_step_series: bad precision");
+    if (d.area_source != CG_AREA_PIXEL && d.area_source != CG_AREA_POLYGON) return fail(c, CG_EINVAL, "cg_step_series: bad area source");
+    if (!(d.tol > 0) || d.patience < 0 || d.max_iters < 0 || d.fixed_iters < 0 || !(d.shape >= 0))
+      return fail(c, CG_EINVAL, "cg_step_series: bad stopping parameters");
+    if (d.frames >= 2 && !out[i].frames) return fail(c, CG_EINVAL, "cg_step_series: frames requested without a buffer");
+    if (d.init_field && d.init_G < 1) return fail(c, CG_EINVAL, "cg_step_series: init_field needs init_G >= 1");
+    if ((int64_t)d.map->n_vert + d.n_extra > INT32_MAX) return fail(c, CG_EINVAL, "cg_step_series: too many points");
+  }
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  for (int prec = CG_F32; prec <= CG_F64; ++prec) {
+    // direct steps of every series with this precision: one batch
+    std::vector<Spec> specs;
+    std::vector<StepRef> refs;
+    int max_t = 0;
+    for (int i = 0; i < n_series; ++i) {
+      if (desc[i].precision != prec) continue;
+      if (desc[i].mode == CG_DIRECT) {
+        for (int t = 0; t < desc[i].n_steps; ++t) {
+          specs.push_back(spec_for(desc[i], out[i], t, false));
+          refs.push_back({i, t});
+        }
+      } else {
+        max_t = std::max(max_t, desc[i].n_steps);
+      }
+    }
+    int rc = run_batch(c, specs, refs, desc, out, prec, graph_iters, st);
+    if (rc) return rc;
+    // cumulative series: step t of all of them together, in order
+    for (int t = 0; t < max_t; ++t) {
+      specs.clear();
+      refs.clear();
+      for (int i = 0; i < n_series; ++i) {
+        if (desc[i].precision != prec || desc[i].mode != CG_CUMULATIVE || t >= desc[i].n_steps) continue;
+        specs.push_back(spec_for(desc[i], out[i], t, true));
+        refs.push_back({i, t});
+      }
+      rc = run_batch(c, specs, refs, desc, out, prec, graph_iters, st);
+      if (rc) return rc;
+    }
+  }
+  for (int i = 0; i < n_series; ++i) {
+    const cg_series_desc& d = desc[i];
+    if (d.frames < 2) continue;
+    const int64_t n = d.map->n_vert;
+    for (int t = 1; t < d.n_steps; ++t)
+      cgk::launch_frames(out[i].xy + (size_t)(t - 1) * n * 2, out[i].xy + (size_t)t * n * 2,
+                         out[i].frames + (size_t)(t - 1) * (d.frames - 1) * n * 2, n, d.frames, st);
+  }
+  HIP_OK(c, hipStreamSynchronize(st));
+  return check_launch(c);
+}

@@ -1,0 +1,253 @@
+// Device-side types shared by the HIP kernels of libcg.
+//
+// Every kernel works on a batch of independent cartogram instances.  A
+// launch covers all instances: blockIdx.x is mapped to (instance, local
+// block) through a per-kind prefix table of block counts, so one code path
+// serves a single cartogram, all time steps of a series and uneven batches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cg.h"
+
+namespace cgk {
+
+constexpr int kSub = 256;          // fixed-point subdivisions per pixel (rasteriser)
+constexpr int kLutLds = 2048;      // LUT entries kept in LDS by the scan / fill kernels
+constexpr int kRowXingMax = 1024;  // crossings one row may hold in LDS
+constexpr int kSetCap = 8;         // simultaneous claims tracked per pixel run
+
+// Pipeline stages of one iteration (for per-stage timing hooks).
+enum Stage {
+  ST_RASTER_COUNT = 0, ST_RASTER_SCAN, ST_RASTER_EMIT, ST_RASTER_FILL, ST_DENSITY,
+  ST_SAT_REDUCE, ST_SAT_CARRY1, ST_SAT_CARRY2, ST_SAT_FINAL, ST_MAP, ST_AREAS, ST_ERR, ST_COUNT
+};
+// Called on the host right before (after = 0) and after (after = 1) a
+// stage's kernel is enqueued.
+typedef void (*StageHook)(int stage, int after, void* user);
+
+// Iteration state of one instance (written by the kernels, polled by the host).
+struct IterState {
+  int32_t iter;       // moves done so far
+  int32_t best_k;     // iteration of the smallest max error seen
+  int32_t done;       // stopping rule met
+  int32_t status;     // CG_STATUS_*
+  int32_t flags;      // CG_FLAG_*
+  int32_t evaluated;  // the error of the starting positions is known
+  int64_t contested;  // contested pixels in the latest label map
+  int64_t xings;      // row crossings in the latest label map
+  double xi, eps, best_xi;
+  double d0, C;       // density parameters of the latest iteration
+};
+
+struct Inst {
+  int32_t N, R, n_vert, n_pts;        // n_pts = vertices + tracer points
+  int32_t n_edges, n_rings, n_lut, pad0;
+  int32_t tw, th, ntx, nty;           // integral-image tiling
+  int32_t area_source, patience, max_iters, fixed_iters;
+  float shape, tol;
+  int64_t pitch, xing_cap;
+  // topology
+  const int4* edges;                  // (v0, v1, region A, region B)
+  const int32_t* ring_off;
+  const int32_t* ring_idx;
+  const int32_t* reg_ring_off;        // [R+1] region -> rings
+  const int32_t* reg_rings;
+  // state and buffers
+  float2* xy;                         // [n_vert] vertex positions (iterated in place)
+  float2* extra;                      // [n_pts - n_vert] tracer points moved along
+  const float2* src_xy;               // starting positions copied in by k_init (or null)
+  const float2* src_extra;
+  const float* init_field;            // warm-start displacement [2][G+1][G+1] or null
+  int64_t init_G;
+  const float* values;                // [R]
+  uint32_t* row_cnt;                  // [N]
+  uint32_t* row_off;                  // [N+1]
+  uint64_t* xing;                     // [xing_cap]
+  uint16_t* labels;                   // [N][N]
+  int64_t* counts;                    // [R+1]
+  float* lut;                         // [n_lut]
+  const float* density;               // dense texture (replaces labels + lut) or null
+  void* S;
+  void* T;
+  void* HA;
+  void* HB;
+  void* agg;                          // integral-image tile aggregates
+  void* carry;                        // integral-image carries
+  double* areas;                      // [R+1]
+  IterState* st;
+};
+
+// Per-kind block offsets over the instances of a batch ([n+1] each).
+struct Batch {
+  const Inst* inst;
+  int32_t n;
+  int32_t skip_done;                  // 1: instances whose state says done are skipped
+  const int64_t* off_edges;
+  const int64_t* off_rows;
+  const int64_t* off_tiles;
+  const int64_t* off_carry1;
+  const int64_t* off_carry2;
+  const int64_t* off_pts;
+  const int64_t* off_regions;
+  const int64_t* off_inst;
+};
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int n, int64_t b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool inst_done(const Batch& B, const Inst& I) {
+  return B.skip_done && I.st != nullptr && I.st->done != 0;
+}
+
+__device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  return (q * b > a) ? q - 1 : q;
+}
+__device__ __forceinline__ int64_t ceildiv(int64_t a, int64_t b) { return -floordiv(-a, b); }
+
+// ---------------------------------------------------------------------------
+// accumulation precision
+
+struct Comp {  // unevaluated sum hi + lo of two floats
+  float hi, lo;
+};
+
+template <int P> struct PT;
+template <> struct PT<CG_F32> { typedef float acc; typedef float carry; typedef float store; };
+template <> struct PT<CG_COMP> { typedef Comp acc; typedef double carry; typedef float store; };
+template <> struct PT<CG_F64> { typedef double acc; typedef double carry; typedef double store; };
+
+__device__ __forceinline__ void acc_zero(float& a) { a = 0.f; }
+__device__ __forceinline__ void acc_zero(double& a) { a = 0.0; }
+__device__ __forceinline__ void acc_zero(Comp& a) { a.hi = 0.f; a.lo = 0.f; }
+
+// add a density sample
+__device__ __forceinline__ void acc_add(float& a, float x) { a += x; }
+__device__ __forceinline__ void acc_add(double& a, float x) { a += (double)x; }
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+__device__ __forceinline__ void acc_add(Comp& a, float x) {
+  float s, e;
+  two_sum(a.hi, x, s, e);
+  a.hi = s;
+  a.lo += e;
+}
+// add another accumulator
+__device__ __forceinline__ void acc_addv(float& a, float b) { a += b; }
+__device__ __forceinline__ void acc_addv(double& a, double b) { a += b; }
+__device__ __forceinline__ void acc_addv(Comp& a, Comp b) {
+  float s, e;
+  two_sum(a.hi, b.hi, s, e);
+  a.hi = s;
+  a.lo += e + b.lo;
+}
+__device__ __forceinline__ float acc_sub(float a, float b) { return a - b; }
+__device__ __forceinline__ double acc_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ Comp acc_sub(Comp a, Comp b) {
+  Comp nb{-b.hi, -b.lo};
+  acc_addv(a, nb);
+  return a;
+}
+__device__ __forceinline__ float acc_half(float a) { return 0.5f * a; }
+__device__ __forceinline__ double acc_half(double a) { return 0.5 * a; }
+__device__ __forceinline__ Comp acc_half(Comp a) { return Comp{0.5f * a.hi, 0.5f * a.lo}; }
+
+// conversions between accumulator, carry and storage types
+__device__ __forceinline__ float to_carry(float a) { return a; }
+__device__ __forceinline__ double to_carry(double a) { return a; }
+__device__ __forceinline__ double to_carry(Comp a) { return (double)a.hi + (double)a.lo; }
+__device__ __forceinline__ void from_carry(float& a, float c) { a = c; }
+__device__ __forceinline__ void from_carry(double& a, double c) { a = c; }
+__device__ __forceinline__ void from_carry(Comp& a, double c) {
+  a.hi = (float)c;
+  a.lo = (float)(c - (double)a.hi);
+}
+__device__ __forceinline__ float to_store(float a) { return a; }
+__device__ __forceinline__ double to_store(double a) { return a; }
+__device__ __forceinline__ float to_store(Comp a) { return (float)((double)a.hi + (double)a.lo); }
+
+__device__ __forceinline__ float shfl_up_acc(float v, int d) { return __shfl_up(v, d, 64); }
+__device__ __forceinline__ double shfl_up_acc(double v, int d) { return __shfl_up(v, d, 64); }
+__device__ __forceinline__ Comp shfl_up_acc(Comp v, int d) {
+  return Comp{__shfl_up(v.hi, d, 64), __shfl_up(v.lo, d, 64)};
+}
+
+__device__ __forceinline__ float shfl_acc(float v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ double shfl_acc(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ Comp shfl_acc(Comp v, int src) {
+  return Comp{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
+}
+
+// Exclusive scan of one value per lane over a 64-wide wavefront (fixed order).
+template <typename A>
+__device__ __forceinline__ A wave_exclusive_scan(A v, int lane) {
+  A x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    A t = shfl_up_acc(x, d);
+    if (lane >= d) acc_addv(x, t);
+  }
+  A ex = shfl_up_acc(x, 1);
+  if (lane == 0) acc_zero(ex);
+  return ex;
+}
+
+// XCD-aware block order: consecutive logical tiles land on the same XCD
+// (the hardware deals blocks round-robin over the 8 XCDs), so halo reads
+// of neighbouring tiles hit the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  constexpr int64_t X = 8;
+  int64_t per = nblocks / X;
+  if (per == 0 || b >= per * X) return b;
+  return (b % X) * per + b / X;
+}
+
+// Integral-image tiling of one texture: tiles of TW columns x TH rows,
+// padded extents NX = ntx*TW >= N, NY = nty*TH >= N; index ranges of the
+// anti-diagonal (u = i+j-1 in [-1, NX+NY-1]) and diagonal (v = i-j in
+// [-NY, NX]) carries.  Scratch arrays hold elements of the carry type.
+struct SatLayout {
+  int32_t ntx, nty, NX, NY, LA, LB;
+  int64_t rowTot, RC, tileTot, prefTot, colsum, cdfA, cdfB, Cval, agg_elems;
+  int64_t Stop, TAc, TBc, carry_elems;
+};
+
+__host__ __device__ inline SatLayout sat_layout(int N, int TW, int TH) {
+  SatLayout L;
+  L.ntx = (N + TW - 1) / TW;
+  L.nty = (N + TH - 1) / TH;
+  L.NX = L.ntx * TW;
+  L.NY = L.nty * TH;
+  L.LA = L.NX + L.NY + 1;
+  L.LB = L.NX + L.NY + 1;
+  const int64_t ntx = L.ntx, nty = L.nty, D = TW + TH - 1;
+  int64_t o = 0;
+  L.rowTot = o; o += ntx * L.NY;
+  L.RC = o; o += ntx * L.NY;
+  L.tileTot = o; o += nty * ntx;
+  L.prefTot = o; o += nty * (ntx + 1);
+  L.colsum = o; o += nty * ntx * (TW + 1);
+  L.cdfA = o; o += nty * ntx * D;
+  L.cdfB = o; o += nty * ntx * D;
+  L.Cval = o; o += 1;
+  L.agg_elems = o;
+  o = 0;
+  L.Stop = o; o += nty * (int64_t)(L.NX + 1);
+  L.TAc = o; o += (nty + 1) * (int64_t)L.LA;
+  L.TBc = o; o += (nty + 1) * (int64_t)L.LB;
+  L.carry_elems = o;
+  return L;
+}
+
+}  // namespace cgk

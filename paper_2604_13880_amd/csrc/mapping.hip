@@ -1,0 +1,346 @@
+// Density, displacement, advection, areas and the stopping rule
+// (paper: Method, Steps 1, 3, 5, 6, 7; Background, eqs.(2)-(3) and
+// "Quality Measures").
+#include "cg_dev.h"
+
+namespace cgk {
+
+// Fixed-order block reductions over 256 threads (deterministic).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Step 3: density LUT.  d0 = sum s / sum o over map regions with o > 0,
+// background density b*d0; the LUT is scaled so the texture mass is N^2
+// (the map is invariant to a common scale of the density).
+__global__ __launch_bounds__(256) void k_density(Batch B) {
+  const int k = find_inst(B.off_inst, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  if (inst_done(B, I)) return;
+  __shared__ double red[256];
+  const int t = threadIdx.x, R = I.R;
+  const double NN = (double)I.N * (double)I.N;
+  const bool poly = I.area_source == CG_AREA_POLYGON;
+  double ss = 0.0, so = 0.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    if (o > 0.0) ss += (double)I.values[v - 1];
+    so += o;
+  }
+  ss = block_sum(ss, red);
+  so = block_sum(so, red);
+  const double d0 = so > 0.0 ? ss / so : 1.0;
+  const double bdv = (double)I.shape * d0;
+  double cm = 0.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    if (o > 0.0) cm += (double)I.values[v - 1] / o * (double)I.counts[v];
+  }
+  cm = block_sum(cm, red) + bdv * (double)I.counts[0];
+  const double kappa = cm > 0.0 ? NN / cm : 1.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    I.lut[v] = o > 0.0 ? (float)(kappa * ((double)I.values[v - 1] / o)) : 0.f;
+  }
+  for (int v = R + 1 + t; v < I.n_lut; v += 256) I.lut[v] = 0.f;
+  if (t == 0) {
+    I.lut[0] = (float)(kappa * bdv);
+    I.st->d0 = d0;
+    I.st->C = cm;
+  }
+}
+
+// Step 1 in closed form: t(x, y; d0) for a constant density, from the
+// quadrant areas (products) and wedge areas (squares minus the parts the
+// domain border cuts off), combined by eq.(2).
+template <typename F>
+__device__ __forceinline__ void anchors(F x, F y, F& q1x, F& q1y, F& q2x, F& q2y, F& q3x, F& q3y,
+                                        F& q4x, F& q4y) {
+  if (y < x) { q1x = 1; q1y = 1 + y - x; q3x = x - y; q3y = 0; }
+  else { q1x = 1 - y + x; q1y = 1; q3x = 0; q3y = y - x; }
+  if (x + y < 1) { q2x = x + y; q2y = 0; q4x = 0; q4y = x + y; }
+  else { q2x = 1; q2y = x + y - 1; q4x = x + y - 1; q4y = 1; }
+}
+
+template <typename F>
+__device__ __forceinline__ F sqp(F z) { return z > F(0) ? z * z : F(0); }
+
+template <typename F>
+__device__ __forceinline__ void t_uniform(F x, F y, F q1x, F q1y, F q2x, F q2y, F q3x, F q3y, F q4x,
+                                          F q4y, F& tx, F& ty) {
+  const F h = F(0.5);
+  const F a = x * y, b = x * (1 - y), g = (1 - x) * (1 - y), d = (1 - x) * y;
+  const F at = y * y - h * sqp(y - x) - h * sqp(x + y - 1);
+  const F bt = x * x - h * sqp(x - y) - h * sqp(x + y - 1);
+  const F gt = (1 - y) * (1 - y) - h * sqp(1 - x - y) - h * sqp(x - y);
+  const F dt = (1 - x) * (1 - x) - h * sqp(1 - x - y) - h * sqp(y - x);
+  tx = h * (a * q1x + b * q2x + g * q3x + d * q4x + (at + gt) * x + bt);
+  ty = h * (a * q1y + b * q2y + g * q3y + d * q4y + at + (bt + dt) * y);
+}
+
+// Steps 5 at one node: D = t(.; d) - t(.; d0) (eqs.(2)-(3)).
+template <typename F>
+__device__ __forceinline__ void node_disp(const F* S, const F* T, const F* HA, const F* HB, int64_t pitch,
+                                          int N, F C, int i, int j, F& dx, F& dy) {
+  const F invN = F(1) / F(N);
+  const F x = F(i) * invN, y = F(j) * invN;
+  const F s = S[(int64_t)j * pitch + i];
+  const F siN = S[(int64_t)N * pitch + i];
+  const F sNj = S[(int64_t)j * pitch + N];
+  const F tt = T[(int64_t)j * pitch + i];
+  const F ha = HA[i + j];
+  const F hb = HB[j - i + N];
+  const F a = s, b = siN - s, dl = sNj - s, g = C - siN - sNj + s;
+  const F at = tt, bt = ha - tt, dt = hb - tt, gt = C - ha - hb + tt;
+  F q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y;
+  anchors(x, y, q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y);
+  const F inv2C = F(1) / (F(2) * C);
+  const F tx = (a * q1x + b * q2x + g * q3x + dl * q4x + (at + gt) * x + bt) * inv2C;
+  const F ty = (a * q1y + b * q2y + g * q3y + dl * q4y + at + (bt + dt) * y) * inv2C;
+  F ux, uy;
+  t_uniform(x, y, q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y, ux, uy);
+  dx = tx - ux;
+  dy = ty - uy;
+}
+
+// Step 6: bilinear interpolation of D at each point, clamp to [0,1]^2.
+template <typename F>
+__global__ __launch_bounds__(256) void k_map_points(Batch B) {
+  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  if (inst_done(B, I)) return;
+  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  if (idx >= I.n_pts) return;
+  float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
+  const float2 p = *ptr;
+  const int N = I.N;
+  const F fN = F(N);
+  const F u = fmin(fmax(F(p.x) * fN, F(0)), fN);
+  const F v = fmin(fmax(F(p.y) * fN, F(0)), fN);
+  const int i0 = min((int)floor(u), N - 1);
+  const int j0 = min((int)floor(v), N - 1);
+  const F fx = u - F(i0), fy = v - F(j0);
+  const F* S = (const F*)I.S;
+  const F* T = (const F*)I.T;
+  const F* HA = (const F*)I.HA;
+  const F* HB = (const F*)I.HB;
+  const int64_t pitch = I.pitch;
+  const F C = S[(int64_t)N * pitch + N];
+  F d00x, d00y, d10x, d10y, d01x, d01y, d11x, d11y;
+  node_disp(S, T, HA, HB, pitch, N, C, i0, j0, d00x, d00y);
+  node_disp(S, T, HA, HB, pitch, N, C, i0 + 1, j0, d10x, d10y);
+  node_disp(S, T, HA, HB, pitch, N, C, i0, j0 + 1, d01x, d01y);
+  node_disp(S, T, HA, HB, pitch, N, C, i0 + 1, j0 + 1, d11x, d11y);
+  const F w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+  const F dx = w00 * d00x + w10 * d10x + w01 * d01x + w11 * d11x;
+  const F dy = w00 * d00y + w10 * d10y + w01 * d01y + w11 * d11y;
+  float2 o;
+  o.x = (float)fmin(fmax(F(p.x) + dx, F(0)), F(1));
+  o.y = (float)fmin(fmax(F(p.y) + dy, F(0)), F(1));
+  *ptr = o;
+}
+
+// Warm start: move every point by a given displacement field sampled at
+// the nodes of a G x G grid ([2][G+1][G+1]), bilinearly, then clamp.
+__global__ __launch_bounds__(256) void k_apply_field(Batch B) {
+  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  if (I.init_field == nullptr) return;
+  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  if (idx >= I.n_pts) return;
+  float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
+  const float2 p = *ptr;
+  const int G = (int)I.init_G;
+  const float u = fminf(fmaxf(p.x * G, 0.f), (float)G), v = fminf(fmaxf(p.y * G, 0.f), (float)G);
+  const int i0 = min((int)floorf(u), G - 1), j0 = min((int)floorf(v), G - 1);
+  const float fx = u - i0, fy = v - j0;
+  const int64_t P = (int64_t)(G + 1) * (G + 1);
+  const float* F0 = I.init_field;
+  auto at = [&](int c, int i, int j) { return F0[c * P + (int64_t)j * (G + 1) + i]; };
+  const float w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+  const float dx = w00 * at(0, i0, j0) + w10 * at(0, i0 + 1, j0) + w01 * at(0, i0, j0 + 1) + w11 * at(0, i0 + 1, j0 + 1);
+  const float dy = w00 * at(1, i0, j0) + w10 * at(1, i0 + 1, j0) + w01 * at(1, i0, j0 + 1) + w11 * at(1, i0 + 1, j0 + 1);
+  *ptr = make_float2(fminf(fmaxf(p.x + dx, 0.f), 1.f), fminf(fmaxf(p.y + dy, 0.f), 1.f));
+}
+
+// Shoelace area of every region (sum over its rings), FP64, fixed order.
+__global__ __launch_bounds__(256) void k_areas(Batch B) {
+  const int k = find_inst(B.off_regions, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  if (inst_done(B, I)) return;
+  __shared__ double red[256];
+  const int v = 1 + (int)(blockIdx.x - B.off_regions[k]);
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int rr = I.reg_ring_off[v - 1]; rr < I.reg_ring_off[v]; ++rr) {
+    const int r = I.reg_rings[rr];
+    const int beg = I.ring_off[r], len = I.ring_off[r + 1] - beg;
+    for (int e = t; e < len; e += 256) {
+      const float2 a = I.xy[I.ring_idx[beg + e]];
+      const float2 b = I.xy[I.ring_idx[beg + (e + 1 == len ? 0 : e + 1)]];
+      acc += (double)a.x * (double)b.y - (double)b.x * (double)a.y;
+    }
+  }
+  acc = block_sum(acc, red);
+  if (t == 0) I.areas[v] = 0.5 * acc;
+}
+
+// Cartographic errors and the stopping rule (Method, end of the static
+// construction).  mode 0: update the iteration state; mode 1: evaluate
+// only (eps, xi into the state, nothing else touched).
+__global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
+  const int k = find_inst(B.off_inst, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  if (inst_done(B, I)) return;
+  __shared__ double red[256];
+  const int t = threadIdx.x, R = I.R;
+  double sa = 0.0, ss = 0.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    sa += I.areas[v];
+    ss += (double)I.values[v - 1];
+  }
+  sa = block_sum(sa, red);
+  ss = block_sum(ss, red);
+  double se = 0.0, me = 0.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    const double A = I.areas[v];
+    const double w = (double)I.values[v - 1] * sa / ss;
+    const double m = fmax(A, w);
+    const double e = m > 0.0 ? fabs(A - w) / m : 0.0;
+    se += e;
+    me = fmax(me, e);
+  }
+  se = block_sum(se, red);
+  me = block_max(me, red);
+  if (t != 0) return;
+  IterState* st = I.st;
+  const double xi = me, eps = R > 0 ? se / R : 0.0;
+  I.areas[0] = 1.0 - sa;
+  st->xi = xi;
+  st->eps = eps;
+  if (mode == 1) return;
+  int it;
+  if (!st->evaluated) {
+    st->evaluated = 1;
+    it = 0;
+    st->best_xi = xi;
+    st->best_k = 0;
+  } else {
+    it = st->iter + 1;
+    st->iter = it;
+    if (xi < st->best_xi) {
+      st->best_xi = xi;
+      st->best_k = it;
+    }
+  }
+  int done = 0, status = CG_STATUS_MAXITER;
+  if (st->flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
+  else if (I.fixed_iters > 0) { done = it >= I.fixed_iters; status = CG_STATUS_MAXITER; }
+  else if (xi < (double)I.tol) { done = 1; status = CG_STATUS_CONVERGED; }
+  else if (it - st->best_k >= I.patience) { done = 1; status = CG_STATUS_STALLED; }
+  else if (it >= I.max_iters) { done = 1; status = CG_STATUS_MAXITER; }
+  st->status = status;
+  st->done = done;
+}
+
+// Reset the iteration state and copy the starting positions.
+__global__ __launch_bounds__(256) void k_init(Batch B) {
+  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  const Inst& I = B.inst[k];
+  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  if (idx == 0) {
+    IterState z = {};
+    z.best_xi = 1e300;
+    *I.st = z;
+  }
+  // the row counters are accumulated with atomics and cleared by their
+  // consumers; scratch memory starts with arbitrary contents
+  if (I.row_cnt) {
+    const int64_t nth = (B.off_pts[k + 1] - B.off_pts[k]) * 256;
+    for (int64_t q = idx; q < I.N; q += nth) I.row_cnt[q] = 0u;
+  }
+  if (idx >= I.n_pts) return;
+  if (idx < I.n_vert) {
+    if (I.src_xy && I.src_xy != I.xy) I.xy[idx] = I.src_xy[idx];
+  } else {
+    const int64_t e = idx - I.n_vert;
+    if (I.src_extra && I.src_extra != I.extra) I.extra[e] = I.src_extra[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_export(Batch B, int64_t* contested, double* eps_xi) {
+  const IterState* st = B.inst[0].st;
+  if (threadIdx.x == 0) {
+    if (contested) *contested = st->contested;
+    if (eps_xi) {
+      eps_xi[0] = st->eps;
+      eps_xi[1] = st->xi;
+    }
+  }
+}
+
+// Transition frames: f = a + (k/K)(b - a), k = 1..K-1, for n points.
+__global__ __launch_bounds__(256) void k_frames(const float2* a, const float2* b, float2* out, int64_t n, int K) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const float2 pa = a[idx], pb = b[idx];
+  for (int kk = 1; kk < K; ++kk) {
+    const float w = (float)kk / (float)K;
+    out[(int64_t)(kk - 1) * n + idx] = make_float2(pa.x + w * (pb.x - pa.x), pa.y + w * (pb.y - pa.y));
+  }
+}
+
+// host launchers --------------------------------------------------------------
+
+void launch_density(const Batch& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_density, dim3(B.n), dim3(256), 0, s, B);
+}
+void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s) {
+  if (pt_blocks <= 0) return;
+  if (prec == CG_F64) hipLaunchKernelGGL(k_map_points<double>, dim3(pt_blocks), dim3(256), 0, s, B);
+  else hipLaunchKernelGGL(k_map_points<float>, dim3(pt_blocks), dim3(256), 0, s, B);
+}
+void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s) {
+  if (pt_blocks > 0) hipLaunchKernelGGL(k_apply_field, dim3(pt_blocks), dim3(256), 0, s, B);
+}
+void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s) {
+  if (region_blocks > 0) hipLaunchKernelGGL(k_areas, dim3(region_blocks), dim3(256), 0, s, B);
+}
+void launch_err(const Batch& B, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_err, dim3(B.n), dim3(256), 0, s, B, mode);
+}
+void launch_init(const Batch& B, int64_t pt_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(pt_blocks), dim3(256), 0, s, B);
+}
+void launch_export(const Batch& B, int64_t* contested, double* eps_xi, hipStream_t s) {
+  hipLaunchKernelGGL(k_export, dim3(1), dim3(64), 0, s, B, contested, eps_xi);
+}
+void launch_frames(const float* a, const float* b, float* out, int64_t n, int K, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0 && K > 1)
+    hipLaunchKernelGGL(k_frames, dim3(blocks), dim3(256), 0, s, (const float2*)a, (const float2*)b,
+                       (float2*)out, n, K);
+}
+
+}  // namespace cgk
