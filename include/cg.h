@@ -44,10 +44,11 @@ extern "C" {
 #define CG_EUNSUPPORTED (-4)
 
 /* Accumulation precision of the integral images (tables stored as float
- * for F32/COMP, double for F64). */
-#define CG_F32 0  /* float accumulation */
-#define CG_COMP 1 /* compensated float (TwoSum) accumulation, float carries in double */
-#define CG_F64 2  /* double accumulation and storage */
+ * for F32/COMP/F64ACC, double for F64). */
+#define CG_F32 0    /* float accumulation */
+#define CG_COMP 1   /* compensated float (TwoSum) accumulation, float carries in double */
+#define CG_F64 2    /* double accumulation and storage */
+#define CG_F64ACC 3 /* double accumulation, float storage */
 
 #define CG_DIRECT 0     /* every time step deforms the original map */
 #define CG_CUMULATIVE 1 /* every time step starts from the previous cartogram */
@@ -110,7 +111,7 @@ int cg_rasterize(cg_ctx* ctx, const cg_map* map, const float* xy, int N, uint16_
                  int64_t* counts, int64_t* contested, void* stream);
 
 /* Node integral images of one texture (Background, "Integral Images",
- * eq.(1)).  Element type: float for CG_F32/CG_COMP, double for CG_F64.
+ * eq.(1)).  Element type: double for CG_F64, float otherwise.
  *   S  [(N+1)][pitch]: S[j][i] = integral of d over [0,i] x [0,j]
  *   T  [(N+1)][pitch]: integral of d over the top wedge of node (i,j),
  *                      { (x',y') : y' <= j - |x' - i| }
@@ -135,8 +136,9 @@ int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size
 /* Step 4: integral images of the density texture.  Either labels (uint16
  * [N][N]) with lut (float [n_lut] density per label; every label must be
  * < n_lut), or, when `density` is not NULL, a dense float [N][N]
- * texture (labels/lut ignored).  out->S, T, HA, HB are caller buffers of
- * cg_inim_size's sizes; out->N/precision/pitch are filled in. */
+ * texture (labels/lut ignored); labels / density must be 16-byte
+ * aligned.  out->S, T, HA, HB are caller buffers of cg_inim_size's sizes;
+ * out->N/precision/pitch are filled in. */
 int cg_integral_image(cg_ctx* ctx, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
                       const float* density, int precision, cg_inim* out, void* stream);
 
@@ -201,11 +203,17 @@ typedef struct {
 int cg_step_series(cg_ctx* ctx, const cg_series_desc* desc, int n_series, cg_series_out* out,
                    int32_t graph_iters, void* stream);
 
-/* Integral-image tile shape used for (N, batch pixel count); the
- * autotuner (cg_autotune) fills the table, defaults otherwise.  Both may
- * be called at any time; cg_autotune times every candidate shape on
- * synthetic textures (blocking). */
+/* Integral-image tile shape (TW columns x TH rows per tile) used for a
+ * launch whose largest texture side is N and whose textures hold
+ * batch_pixels pixels in total.  The table is per context: cg_autotune
+ * times every supported shape on a synthetic batch of `batch` label maps
+ * of side N (blocking) and records the fastest, reading and appending
+ * "arch N precision batch_pixels tw th" lines in cache_path when it is
+ * not NULL; cg_set_tile_shape records a shape directly; other launches
+ * use the nearest recorded batch size for (N, precision), else a
+ * default.  Supported shapes: 64x16, 128x16, 128x32, 256x32, 256x64. */
 int cg_tile_shape(const cg_ctx* ctx, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th);
+int cg_set_tile_shape(cg_ctx* ctx, int N, int precision, int64_t batch_pixels, int32_t tw, int32_t th);
 int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* cache_path);
 
 /* Timing of one pipeline stage inside cg_step_series (profiling aid).

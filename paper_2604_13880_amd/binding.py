@@ -19,7 +19,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcg.so")
 
-F32, COMP, F64 = 0, 1, 2
+F32, COMP, F64, F64ACC = 0, 1, 2, 3
 DIRECT, CUMULATIVE = 0, 1
 AREA_PIXEL, AREA_POLYGON = 0, 1
 STATUS_CONVERGED, STATUS_STALLED, STATUS_MAXITER, STATUS_ERROR = 0, 1, 2, 3
@@ -73,6 +73,7 @@ def lib():
             "cg_step_series": (C.c_int, [vp, C.POINTER(CgSeriesDesc), C.c_int, C.POINTER(CgSeriesOut), i32, vp]),
             "cg_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, C.POINTER(i32), C.POINTER(i32)]),
             "cg_autotune": (C.c_int, [vp, C.c_int, C.c_int, i32, C.c_char_p]),
+            "cg_set_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, i32, i32]),
             "cg_profile_stage": (C.c_int, [vp, C.c_char_p]),
             "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
         }
@@ -87,7 +88,7 @@ def lib():
 def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
             "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
-            "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_autotune", "cg_profile_stage",
+            "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
             "cg_profile_read"]
 
 
@@ -265,6 +266,15 @@ class Context:
         self._check(lib().cg_tile_shape(self.handle, int(N), int(precision), int(batch_pixels),
                                         C.byref(tw), C.byref(th)), "cg_tile_shape")
         return tw.value, th.value
+
+    def set_tile_shape(self, N: int, precision: int, batch_pixels: int, tw: int, th: int):
+        self._check(lib().cg_set_tile_shape(self.handle, int(N), int(precision), int(batch_pixels), int(tw), int(th)),
+                    "cg_set_tile_shape")
+
+    def autotune(self, N: int, precision: int, batch: int = 1, cache_path: str | None = None):
+        self._check(lib().cg_autotune(self.handle, int(N), int(precision), int(batch),
+                                      None if cache_path is None else cache_path.encode()), "cg_autotune")
+        return self.tile_shape(N, precision, int(N) * int(N) * int(batch))
 
     def step_series(self, series: list[dict], graph_iters: int = 8):
         """Run cartogram series.  Each dict: map (Map), xy0 (float32 [n,2]),

@@ -50,7 +50,7 @@ struct DevBuf {
   size_t n = 0;
 };
 
-constexpr int kFillRows = 4;
+using cgk::kFillRows;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -151,7 +151,7 @@ int upload(cg_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t st) 
 bool pow2_ok(int N) { return N >= 16 && N <= 8192 && (N & (N - 1)) == 0; }
 
 size_t store_size(int prec) { return prec == CG_F64 ? 8 : 4; }
-size_t carry_size(int prec) { return prec == CG_F32 ? 4 : 8; }
+size_t carry_size(int prec) { return prec == CG_F32 ? 4 : 8; }  // COMP, F64, F64ACC carry in double
 
 // ---------------------------------------------------------------------------
 // plans
@@ -323,7 +323,7 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
         (I.N + kFillRows - 1) / kFillRows,
         (int64_t)L.ntx * L.nty,
         (L.NY + L.nty + 1 + 255) / 256,
-        (L.NX + 1 + (int64_t)L.LA + L.LB + 255) / 256,
+        (L.NX + 1 + (int64_t)L.LA + L.LB + (256 / L.carry_ch) - 1) / (256 / L.carry_ch),
         std::max<int64_t>(1, (I.n_pts + 255) / 256),
         I.R,
         1};
@@ -584,7 +584,7 @@ int cg_rasterize(cg_ctx* c, const cg_map* map, const float* xy, int N, uint16_t*
 }
 
 int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size_t* marginal_bytes) {
-  if (!pow2_ok(N) || precision < CG_F32 || precision > CG_F64) return CG_EINVAL;
+  if (!pow2_ok(N) || precision < CG_F32 || precision > CG_F64ACC) return CG_EINVAL;
   const int64_t p = pitch_of(N);
   if (pitch) *pitch = p;
   if (table_bytes) *table_bytes = store_size(precision) * (size_t)(N + 1) * p;
@@ -597,9 +597,11 @@ int cg_integral_image(cg_ctx* c, int N, const uint16_t* labels, const float* lut
   if (!c) return CG_EINVAL;
   if (!out || !out->S || !out->T || !out->HA || !out->HB) return fail(c, CG_EINVAL, "cg_integral_image: output buffers missing");
   if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_integral_image: N must be a power of two in [16, 8192]");
-  if (precision < CG_F32 || precision > CG_F64) return fail(c, CG_EINVAL, "cg_integral_image: bad precision");
+  if (precision < CG_F32 || precision > CG_F64ACC) return fail(c, CG_EINVAL, "cg_integral_image: bad precision");
   if (!density && (!labels || !lut || n_lut < 1 || n_lut > 65536))
     return fail(c, CG_EINVAL, "cg_integral_image: need labels + lut (1 <= n_lut <= 65536) or a density texture");
+  if (((uintptr_t)labels | (uintptr_t)density) & 15)
+    return fail(c, CG_EINVAL, "cg_integral_image: labels / density must be 16-byte aligned");
   hipSetDevice(c->device);
   hipStream_t st = pick_stream(c, stream);
   int tw, th;
@@ -633,7 +635,7 @@ int cg_map_points(cg_ctx* c, const cg_inim* im, const float* xy_in, float* xy_ou
                   void* stream) {
   if (!c) return CG_EINVAL;
   if (!im || !xy_in || !xy_out || n_points < 0) return fail(c, CG_EINVAL, "cg_map_points: bad arguments");
-  if (!pow2_ok(im->N) || im->precision < CG_F32 || im->precision > CG_F64 || im->pitch < im->N + 1 ||
+  if (!pow2_ok(im->N) || im->precision < CG_F32 || im->precision > CG_F64ACC || im->pitch < im->N + 1 ||
       !im->S || !im->T || !im->HA || !im->HB)
     return fail(c, CG_EINVAL, "cg_map_points: bad integral-image descriptor");
   if (n_points == 0) return CG_OK;
@@ -693,9 +695,105 @@ int cg_region_areas(cg_ctx* c, const cg_map* map, const float* xy, const float* 
   return check_launch(c);
 }
 
+static const int kShapes[][2] = {{64, 16}, {128, 16}, {128, 32}, {256, 32}, {256, 64}};
+
+int cg_set_tile_shape(cg_ctx* c, int N, int precision, int64_t batch_pixels, int32_t tw, int32_t th) {
+  if (!c) return CG_EINVAL;
+  if (!pow2_ok(N) || precision < CG_F32 || precision > CG_F64ACC || batch_pixels < 0 ||
+      !cgk::sat_shape_supported(tw, th))
+    return fail(c, CG_EINVAL, "cg_set_tile_shape: bad arguments or unsupported shape");
+  c->tiles[std::make_tuple(N, precision, batch_pixels)] = {tw, th};
+  return CG_OK;
+}
+
 int cg_autotune(cg_ctx* c, int N, int precision, int32_t batch, const char* cache_path) {
-  (void)N; (void)precision; (void)batch; (void)cache_path;
-  return fail(c, CG_EUNSUPPORTED, "cg_autotune: not available");
+  if (!c) return CG_EINVAL;
+  if (!pow2_ok(N) || precision < CG_F32 || precision > CG_F64ACC || batch < 1 || batch > 4096)
+    return fail(c, CG_EINVAL, "cg_autotune: bad arguments");
+  const int64_t px = (int64_t)N * N * batch;
+  hipDeviceProp_t prop;
+  HIP_OK(c, hipGetDeviceProperties(&prop, c->device));
+  const std::string arch = prop.gcnArchName;
+  std::string key;
+  {
+    std::ostringstream os;
+    os << arch.substr(0, arch.find(':')) << " " << N << " " << precision << " " << px;
+    key = os.str();
+  }
+  if (cache_path) {  // "arch N precision batch_pixels tw th" per line
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream is(line);
+      std::string a;
+      int n, p, tw, th;
+      int64_t b;
+      if (is >> a >> n >> p >> b >> tw >> th) {
+        std::ostringstream os;
+        os << a << " " << n << " " << p << " " << b;
+        if (os.str() == key && cgk::sat_shape_supported(tw, th)) {
+          c->tiles[std::make_tuple(N, precision, px)] = {tw, th};
+          return CG_OK;
+        }
+      }
+    }
+  }
+  hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, nullptr);
+  // synthetic batch: a label map with a few regions, one LUT
+  char* lab = nullptr;
+  int rc = get_buf(c, "tune:labels", sizeof(uint16_t) * (size_t)N * N, st, &lab);
+  if (rc) return rc;
+  char* lut = nullptr;
+  if ((rc = get_buf(c, "tune:lut", sizeof(float) * 4, st, &lut))) return rc;
+  const float lutv[4] = {1.0f, 3.0f, 0.25f, 7.0f};
+  std::vector<uint16_t> hl((size_t)N * N);
+  for (int q = 0; q < N; ++q)
+    for (int p = 0; p < N; ++p) hl[(size_t)q * N + p] = (uint16_t)(((p * 7) / N + (q * 5) / N) & 3);
+  HIP_OK(c, hipMemcpyAsync(lab, hl.data(), hl.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipMemcpyAsync(lut, lutv, sizeof(lutv), hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipStreamSynchronize(st));
+  hipEvent_t e0, e1;
+  HIP_OK(c, hipEventCreate(&e0));
+  HIP_OK(c, hipEventCreate(&e1));
+  float best = 1e30f;
+  int btw = 0, bth = 0;
+  for (auto& sh : kShapes) {
+    const int tw = sh[0], th = sh[1];
+    if (th > 2 * N && tw > N) continue;
+    std::vector<Spec> specs(batch);
+    for (auto& sp : specs) {
+      sp.N = N;
+      sp.labels = (uint16_t*)lab;
+      sp.lut = (float*)lut;
+      sp.n_lut = 4;
+    }
+    Needs nd;
+    nd.sat = true;
+    Plan P;
+    if ((rc = build_plan(c, specs, precision, tw, th, false, nd, st, P, "tune"))) break;
+    P.B.skip_done = 0;
+    for (int w = 0; w < 2; ++w) cgk::launch_sat(P.B, precision, tw, th, false, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
+    const int reps = 5;
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) cgk::launch_sat(P.B, precision, tw, th, false, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(c, CG_EDEVICE, "cg_autotune: device error"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (ms < best) { best = ms; btw = tw; bth = th; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = check_launch(c))) return rc;
+  c->tiles[std::make_tuple(N, precision, px)] = {btw, bth};
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key << " " << btw << " " << bth << "\n";
+  }
+  return CG_OK;
 }
 
 static const char* kStageNames[cgk::ST_COUNT] = {
@@ -889,7 +987,7 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
     if (!pow2_ok(d.N)) return fail(c, CG_EINVAL, "cg_step_series: N must be a power of two in [16, 8192]");
     if (d.n_steps < 1 || d.map->R < 1) return fail(c, CG_EINVAL, "cg_step_series: need n_steps >= 1 and R >= 1");
     if (d.mode != CG_DIRECT && d.mode != CG_CUMULATIVE) return fail(c, CG_EINVAL, "cg_step_series: bad mode");
-    if (d.precision < CG_F32 || d.precision > CG_F64) return fail(c, CG_EINVAL, "cg_step_series: bad precision");
+    if (d.precision < CG_F32 || d.precision > CG_F64ACC) return fail(c, CG_EINVAL, "cg_step_series: bad precision");
     if (d.area_source != CG_AREA_PIXEL && d.area_source != CG_AREA_POLYGON) return fail(c, CG_EINVAL, "cg_step_series: bad area source");
     if (!(d.tol > 0) || d.patience < 0 || d.max_iters < 0 || d.fixed_iters < 0 || !(d.shape >= 0))
       return fail(c, CG_EINVAL, "cg_step_series: bad stopping parameters");
@@ -899,7 +997,7 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
   }
   hipSetDevice(c->device);
   hipStream_t st = pick_stream(c, stream);
-  for (int prec = CG_F32; prec <= CG_F64; ++prec) {
+  for (int prec = CG_F32; prec <= CG_F64ACC; ++prec) {
     // direct steps of every series with this precision: one batch
     std::vector<Spec> specs;
     std::vector<StepRef> refs;

@@ -14,9 +14,11 @@
 namespace cgk {
 
 constexpr int kSub = 256;          // fixed-point subdivisions per pixel (rasteriser)
-constexpr int kLutLds = 2048;      // LUT entries kept in LDS by the scan / fill kernels
+constexpr int kLutLds = 1024;      // LUT entries kept in LDS by the scan / fill kernels
 constexpr int kRowXingMax = 1024;  // crossings one row may hold in LDS
 constexpr int kSetCap = 8;         // simultaneous claims tracked per pixel run
+constexpr int kFillRows = 4;       // label rows per fill block (one per wavefront)
+constexpr int kCarryRows = 8;      // tile rows one carry thread sums
 
 // Pipeline stages of one iteration (for per-stage timing hooks).
 enum Stage {
@@ -94,13 +96,15 @@ struct Batch {
   const int64_t* off_inst;
 };
 
+// Instance of a (block-uniform) work index; the result is made explicitly
+// wave-uniform so descriptor fields are fetched with scalar loads.
 __device__ __forceinline__ int find_inst(const int64_t* off, int n, int64_t b) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
     if (off[mid] <= b) lo = mid; else hi = mid;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 
 __device__ __forceinline__ bool inst_done(const Batch& B, const Inst& I) {
@@ -124,6 +128,7 @@ template <int P> struct PT;
 template <> struct PT<CG_F32> { typedef float acc; typedef float carry; typedef float store; };
 template <> struct PT<CG_COMP> { typedef Comp acc; typedef double carry; typedef float store; };
 template <> struct PT<CG_F64> { typedef double acc; typedef double carry; typedef double store; };
+template <> struct PT<CG_F64ACC> { typedef double acc; typedef double carry; typedef float store; };
 
 __device__ __forceinline__ void acc_zero(float& a) { a = 0.f; }
 __device__ __forceinline__ void acc_zero(double& a) { a = 0.0; }
@@ -219,6 +224,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
 // [-NY, NX]) carries.  Scratch arrays hold elements of the carry type.
 struct SatLayout {
   int32_t ntx, nty, NX, NY, LA, LB;
+  int32_t carry_ch;        // carry-pass chunks per index (a power of two <= 256)
   int64_t rowTot, RC, tileTot, prefTot, colsum, cdfA, cdfB, Cval, agg_elems;
   int64_t Stop, TAc, TBc, carry_elems;
 };
@@ -231,6 +237,8 @@ __host__ __device__ inline SatLayout sat_layout(int N, int TW, int TH) {
   L.NY = L.nty * TH;
   L.LA = L.NX + L.NY + 1;
   L.LB = L.NX + L.NY + 1;
+  L.carry_ch = 1;
+  while (L.carry_ch * kCarryRows < L.nty) L.carry_ch *= 2;
   const int64_t ntx = L.ntx, nty = L.nty, D = TW + TH - 1;
   int64_t o = 0;
   L.rowTot = o; o += ntx * L.NY;

@@ -36,15 +36,16 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // (the map is invariant to a common scale of the density).
 __global__ __launch_bounds__(256) void k_density(Batch B) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
+  auto count = [&](int v) -> double { return (double)I.counts[v]; };
   const double NN = (double)I.N * (double)I.N;
   const bool poly = I.area_source == CG_AREA_POLYGON;
   double ss = 0.0, so = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    const double o = poly ? I.areas[v] * NN : count(v);
     if (o > 0.0) ss += (double)I.values[v - 1];
     so += o;
   }
@@ -54,13 +55,13 @@ __global__ __launch_bounds__(256) void k_density(Batch B) {
   const double bdv = (double)I.shape * d0;
   double cm = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
-    if (o > 0.0) cm += (double)I.values[v - 1] / o * (double)I.counts[v];
+    const double o = poly ? I.areas[v] * NN : count(v);
+    if (o > 0.0) cm += (double)I.values[v - 1] / o * count(v);
   }
-  cm = block_sum(cm, red) + bdv * (double)I.counts[0];
+  cm = block_sum(cm, red) + bdv * count(0);
   const double kappa = cm > 0.0 ? NN / cm : 1.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    const double o = poly ? I.areas[v] * NN : count(v);
     I.lut[v] = o > 0.0 ? (float)(kappa * ((double)I.values[v - 1] / o)) : 0.f;
   }
   for (int v = R + 1 + t; v < I.n_lut; v += 256) I.lut[v] = 0.f;
@@ -128,7 +129,7 @@ __device__ __forceinline__ void node_disp(const F* S, const F* T, const F* HA, c
 template <typename F>
 __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
 // the nodes of a G x G grid ([2][G+1][G+1]), bilinearly, then clamp.
 __global__ __launch_bounds__(256) void k_apply_field(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void k_apply_field(Batch B) {
 // Shoelace area of every region (sum over its rings), FP64, fixed order.
 __global__ __launch_bounds__(256) void k_areas(Batch B) {
   const int k = find_inst(B.off_regions, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int v = 1 + (int)(blockIdx.x - B.off_regions[k]);
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
 // only (eps, xi into the state, nothing else touched).
 __global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
 // Reset the iteration state and copy the starting positions.
 __global__ __launch_bounds__(256) void k_init(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx == 0) {
     IterState z = {};

@@ -22,8 +22,7 @@
 
 namespace cgk {
 
-constexpr int kFillRows = 4;      // rows per block (one wavefront each)
-constexpr int kFillXing = 512;    // crossings per row held in LDS
+constexpr int kFillXing = 256;    // crossings per row held in LDS
 
 __device__ __forceinline__ int snapc(float v, float scale) { return (int)rintf(v * scale); }
 
@@ -36,7 +35,7 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
 
 __global__ __launch_bounds__(256) void k_raster_count(Batch B) {
   const int k = find_inst(B.off_edges, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
@@ -50,7 +49,7 @@ __global__ __launch_bounds__(256) void k_raster_count(Batch B) {
 
 __global__ __launch_bounds__(1024) void k_raster_scan(Batch B) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ uint32_t wsum[16];
   const int N = I.N, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -97,7 +96,7 @@ __global__ __launch_bounds__(1024) void k_raster_scan(Batch B) {
 
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   const int k = find_inst(B.off_edges, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
@@ -128,146 +127,306 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   }
 }
 
-__device__ __forceinline__ void set_toggle(int* set, int& n, int r, bool& over) {
+// Claim set of the current pixel run.  The common case (at most one
+// claiming region) is a single label `cur`; a run claimed by several regions
+// switches to a small slot array kept in registers (every index is a
+// compile-time constant after unrolling; 0 marks a free slot).
+struct Claims {
+  int cur;           // the claiming region while `multi` is false
+  bool multi;
+  int set[kSetCap];
+};
+
+__device__ __forceinline__ void claims_toggle(Claims& c, int r, bool& over) {
   if (r == 0) return;
-  for (int i = 0; i < n; ++i) {
-    if (set[i] == r) {
-      set[i] = set[n - 1];
-      --n;
-      return;
-    }
+  if (!c.multi) {
+    if (c.cur == 0) { c.cur = r; return; }
+    if (c.cur == r) { c.cur = 0; return; }
+    c.multi = true;
+#pragma unroll
+    for (int i = 0; i < kSetCap; ++i) c.set[i] = 0;
+    c.set[0] = c.cur;
   }
-  if (n < kSetCap) set[n++] = r; else over = true;
+  bool found = false;
+#pragma unroll
+  for (int i = 0; i < kSetCap; ++i)
+    if (c.set[i] == r) {
+      c.set[i] = 0;
+      found = true;
+    }
+  if (!found) {
+    bool placed = false;
+#pragma unroll
+    for (int i = 0; i < kSetCap; ++i)
+      if (!placed && c.set[i] == 0) {
+        c.set[i] = r;
+        placed = true;
+      }
+    if (!placed) over = true;
+  }
+  int n = 0, any = 0;
+#pragma unroll
+  for (int i = 0; i < kSetCap; ++i) {
+    n += c.set[i] != 0;
+    any = max(any, c.set[i]);
+  }
+  if (n <= 1) {  // back to a single claim
+    c.multi = false;
+    c.cur = any;
+  }
 }
 
+__device__ __forceinline__ void claims_label(const Claims& c, int& lab, int& n) {
+  if (!c.multi) {
+    lab = c.cur;
+    n = c.cur != 0;
+    return;
+  }
+  lab = 0;
+  n = 0;
+#pragma unroll
+  for (int i = 0; i < kSetCap; ++i) {
+    lab = max(lab, c.set[i]);
+    n += c.set[i] != 0;
+  }
+}
+
+// One wavefront per row.  Crossings sorted by p0; t = A xor B for every
+// crossing; the inclusive xor-scan X gives the claiming region after every
+// prefix as long as at most one region claims (the claim set starts empty
+// at the left border).  A crossing alone at its p0 keeps the set a
+// singleton iff the label before it is one of its two regions; rows that
+// fail this test, or have several crossings at one p0, take the exact
+// serial walk instead (folded maps, coincident crossings).
 __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   const int k = find_inst(B.off_rows, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  __shared__ uint64_t xs[kFillRows][kFillXing];
-  __shared__ uint64_t srt[kFillRows][kFillXing];
-  __shared__ uint16_t sp_start[kFillRows][kFillXing + 2];
-  __shared__ uint16_t sp_lab[kFillRows][kFillXing + 2];
-  __shared__ int sp_n[kFillRows];
+  constexpr int RPW = kFillRows / 4;   // rows per wavefront
+  __shared__ uint64_t xs[4][kFillXing];
+  __shared__ uint64_t srt[4][kFillXing];
+  __shared__ uint16_t sp_start[4][kFillXing + 2];
+  __shared__ uint16_t sp_lab[4][kFillXing + 2];
   __shared__ uint32_t lcount[kLutLds];
   __shared__ unsigned long long contested_blk;
   const int N = I.N, R = I.R;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int q0 = (int)(blockIdx.x - B.off_rows[k]) * kFillRows;
   const bool lds_counts = (R + 1) <= kLutLds;
   if (lds_counts)
     for (int v = t; v <= R; v += 256) lcount[v] = 0u;
   if (t == 0) contested_blk = 0ull;
-  const int q = (int)(blockIdx.x - B.off_rows[k]) * kFillRows + w;
-  const bool row_ok = q < N;
-  uint32_t cnt = 0, off = 0;
-  bool bad = false;
-  if (row_ok) {
-    cnt = I.row_cnt[q];
-    off = I.row_off[q];
-    if (cnt > (uint32_t)kFillXing || (int64_t)off + cnt > I.xing_cap) bad = true;
-  }
-  if (row_ok && !bad) {
-    for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
-  }
   __syncthreads();
-  if (row_ok && !bad) {
-    // rank sort by (p0, slot): ranks are unique, so srt is a permutation
-    for (uint32_t i = lane; i < cnt; i += 64) {
-      const uint64_t a = xs[w][i];
-      const uint32_t pa = (uint32_t)(a & 0xFFFFu);
-      uint32_t rank = 0;
-      for (uint32_t j = 0; j < cnt; ++j) {
-        const uint32_t pj = (uint32_t)(xs[w][j] & 0xFFFFu);
-        rank += (pj < pa) || (pj == pa && j < i);
-      }
-      srt[w][rank] = a;
+  for (int rr = 0; rr < RPW; ++rr) {
+    const int q = q0 + w * RPW + rr;
+    const bool row_ok = q < N;
+    uint32_t cnt = 0, off = 0;
+    bool bad = false;
+    if (row_ok) {
+      cnt = I.row_cnt[q];
+      off = I.row_off[q];
+      if (cnt > (uint32_t)kFillXing || (int64_t)off + cnt > I.xing_cap) bad = true;
+      if (bad) cnt = 0;
+      for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
     }
-  }
-  __syncthreads();
-  if (row_ok && lane == 0) {
-    int set[kSetCap];
-    int ns = 0, nsp = 0;
-    bool over = false;
-    uint32_t prev = 0;
-    unsigned long long cont = 0;
-    if (!bad) {
-      for (uint32_t i = 0; i <= cnt; ++i) {
-        const uint32_t p0 = i < cnt ? (uint32_t)(srt[w][i] & 0xFFFFu) : (uint32_t)N;
-        if (p0 > prev) {
-          int lab = 0;
-          for (int s = 0; s < ns; ++s) lab = max(lab, set[s]);
-          sp_start[w][nsp] = (uint16_t)prev;
-          sp_lab[w][nsp] = (uint16_t)lab;
-          ++nsp;
-          const uint32_t len = p0 - prev;
-          if (ns > 1) cont += len;
-          if (lds_counts) atomicAdd(&lcount[lab], len);
-          else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)len);
-          prev = p0;
-        }
-        if (i < cnt) {
-          const uint64_t r = srt[w][i];
-          set_toggle(set, ns, (int)((r >> 16) & 0xFFFFu), over);
-          set_toggle(set, ns, (int)((r >> 32) & 0xFFFFu), over);
+    __syncthreads();
+    if (row_ok && cnt <= 64) {
+      // bitonic sort of (p0, slot) keys across the wavefront's lanes
+      const uint64_t rec = lane < (int)cnt ? xs[w][lane] : 0ull;
+      uint64_t key = lane < (int)cnt ? (((rec & 0xFFFFull) << 8) | (uint64_t)lane) : ~0ull;
+      uint64_t val = rec;
+#pragma unroll
+      for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const uint64_t ok2 = __shfl_xor(key, stride, 64);
+          const uint64_t ov = __shfl_xor(val, stride, 64);
+          const bool up = (lane & size) == 0;          // ascending half of this bitonic sequence
+          const bool low = (lane & stride) == 0;        // lower partner
+          const bool take_min = (up == low);
+          const bool swap = take_min ? (ok2 < key) : (ok2 > key);
+          if (swap) {
+            key = ok2;
+            val = ov;
+          }
         }
       }
-    } else {
-      sp_start[w][0] = 0;
-      sp_lab[w][0] = 0;
-      nsp = 1;
-      if (lds_counts) atomicAdd(&lcount[0], (uint32_t)N);
-      else atomicAdd((unsigned long long*)&I.counts[0], (unsigned long long)N);
-    }
-    if (nsp == 0) {  // N == 0 cannot happen; keep the span list well formed
-      sp_start[w][0] = 0;
-      sp_lab[w][0] = 0;
-      nsp = 1;
-    }
-    sp_n[w] = nsp;
-    if (cont) atomicAdd(&contested_blk, cont);
-    if (bad || over) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
-    if (cont) atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
-  }
-  __syncthreads();
-  if (row_ok) {
-    // fill: lane handles 8 consecutive pixels per step
-    const int nsp = sp_n[w];
-    uint16_t* row = I.labels + (int64_t)q * N;
-    for (int p = lane * 8; p < N; p += 64 * 8) {
-      // span containing pixel p: last start <= p
-      int lo = 0, hi = nsp;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (sp_start[w][mid] <= p) lo = mid; else hi = mid;
+      if (lane < (int)cnt) srt[w][lane] = val;
+    } else if (row_ok) {  // rank sort by (p0, slot)
+      for (uint32_t i = lane; i < cnt; i += 64) {
+        const uint64_t a = xs[w][i];
+        const uint32_t pa = (uint32_t)(a & 0xFFFFu);
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < cnt; ++j) {
+          const uint32_t pj = (uint32_t)(xs[w][j] & 0xFFFFu);
+          rank += (pj < pa) || (pj == pa && j < i);
+        }
+        srt[w][rank] = a;
       }
-      uint16_t v[8];
-      int s = lo;
-      for (int c = 0; c < 8; ++c) {
-        while (s + 1 < nsp && sp_start[w][s + 1] <= p + c) ++s;
-        v[c] = sp_lab[w][s];
+    }
+    __syncthreads();
+    if (row_ok) {
+      // xor-scan over the sorted crossings, 64 at a time
+      bool exact = !bad;
+      uint32_t carry = 0, ngroups = 0;
+      for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+        const uint32_t kk = c0 + lane;
+        const bool live = kk < cnt;
+        uint64_t rec = live ? srt[w][kk] : 0ull;
+        const uint32_t p0 = (uint32_t)(rec & 0xFFFFu);
+        const uint32_t ra = (uint32_t)((rec >> 16) & 0xFFFFu), rb = (uint32_t)((rec >> 32) & 0xFFFFu);
+        uint32_t x = live ? (ra ^ rb) : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(x, d, 64);
+          if (lane >= d) x ^= y;
+        }
+        const uint32_t X = x ^ carry;                       // label after this crossing
+        uint32_t Xprev = __shfl_up(X, 1, 64);
+        if (lane == 0) Xprev = carry;
+        const bool last = live && (kk + 1 == cnt || (uint32_t)(srt[w][kk + 1] & 0xFFFFu) != p0);
+        // the lane ending a group of crossings at one p0 replays that group
+        // on the claim set before it ({Xb}, or empty when Xb = 0): the
+        // prefix stays exact iff at most one region claims afterwards
+        bool ok = true;
+        if (last) {
+          Claims cl;
+          cl.multi = false;
+#pragma unroll
+          for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
+          uint32_t xb = X, j = kk;
+          int members = 0;
+          while (true) {
+            const uint64_t rj = srt[w][j];
+            xb ^= (uint32_t)((rj >> 16) & 0xFFFFu) ^ (uint32_t)((rj >> 32) & 0xFFFFu);
+            ++members;
+            if (j == 0 || (uint32_t)(srt[w][j - 1] & 0xFFFFu) != p0 || members > kSetCap) break;
+            --j;
+          }
+          if (members > kSetCap) {
+            ok = false;
+          } else {
+            cl.cur = (int)xb;
+            bool over = false;
+            for (uint32_t i = j; i <= kk; ++i) {
+              const uint64_t ri = srt[w][i];
+              claims_toggle(cl, (int)((ri >> 16) & 0xFFFFu), over);
+              claims_toggle(cl, (int)((ri >> 32) & 0xFFFFu), over);
+            }
+            int lab, n;
+            claims_label(cl, lab, n);
+            ok = !over && n <= 1 && (uint32_t)lab == X;
+          }
+        }
+        (void)Xprev;
+        if (__any(!ok)) exact = false;
+        // runs start at every group's last crossing: span 1 + (groups before)
+        const uint64_t lastmask = __ballot(last);
+        const uint32_t before = ngroups + __popcll(lastmask & ((1ull << lane) - 1ull));
+        if (last) {
+          sp_start[w][1 + before] = (uint16_t)p0;
+          sp_lab[w][1 + before] = (uint16_t)X;
+        }
+        ngroups += __popcll(lastmask);
+        carry = __shfl(X, 63, 64);
       }
-      if (p + 8 <= N) {
+      if (exact) {
+        if (lane == 0) {
+          sp_start[w][0] = 0;
+          sp_lab[w][0] = 0;
+        }
+        // run lengths into the counts
+        for (uint32_t g = lane; g <= ngroups; g += 64) {
+          const uint32_t st0 = g == 0 ? 0u : sp_start[w][g];
+          const uint32_t en = g == ngroups ? (uint32_t)N : sp_start[w][g + 1];
+          const uint32_t lab = g == 0 ? 0u : sp_lab[w][g];
+          if (en > st0) {
+            if (lds_counts) atomicAdd(&lcount[lab], en - st0);
+            else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)(en - st0));
+          }
+        }
+      } else if (lane == 0) {
+        // exact walk of the claim set
+        Claims cl;
+        cl.cur = 0;
+        cl.multi = false;
+#pragma unroll
+        for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
+        bool over = false;
+        uint32_t nsp = 0, prev = 0;
+        unsigned long long cont = 0;
+        for (uint32_t i = 0; i <= cnt; ++i) {
+          uint64_t rec = 0;
+          uint32_t p0 = (uint32_t)N;
+          if (i < cnt) {
+            rec = srt[w][i];
+            p0 = (uint32_t)(rec & 0xFFFFu);
+          }
+          if (p0 > prev || (i == cnt && nsp == 0)) {
+            int lab, n;
+            claims_label(cl, lab, n);
+            sp_start[w][nsp] = (uint16_t)prev;
+            sp_lab[w][nsp] = (uint16_t)lab;
+            ++nsp;
+            const uint32_t len = p0 - prev;
+            if (n > 1) cont += len;
+            if (len) {
+              if (lds_counts) atomicAdd(&lcount[lab], len);
+              else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)len);
+            }
+            prev = p0;
+          }
+          if (i < cnt) {
+            claims_toggle(cl, (int)((rec >> 16) & 0xFFFFu), over);
+            claims_toggle(cl, (int)((rec >> 32) & 0xFFFFu), over);
+          }
+        }
+        ngroups = nsp - 1;
+        if (cont) atomicAdd(&contested_blk, cont);
+        if (bad || over) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+        if (cont) atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+      }
+      ngroups = __shfl(ngroups, 0, 64);
+      // fill: spans 0..ngroups, the last span with start <= p holds pixel p
+      const int nsp = (int)ngroups + 1;
+      uint16_t* row = I.labels + (int64_t)q * N;
+      for (int p = lane * 8; p < N; p += 64 * 8) {
+        int lo = 0, hi = nsp;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (sp_start[w][mid] <= p) lo = mid; else hi = mid;
+        }
+        uint16_t v[8];
+        const uint16_t l0 = sp_lab[w][lo];
+        const int next = lo + 1 < nsp ? (int)sp_start[w][lo + 1] : N;
+        if (next >= p + 8) {   // the 8 pixels lie in one run
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v[c] = l0;
+        } else {
+          int s2 = lo;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            while (s2 + 1 < nsp && sp_start[w][s2 + 1] <= p + c) ++s2;
+            v[c] = sp_lab[w][s2];
+          }
+        }
         uint4 pk;
         pk.x = v[0] | ((uint32_t)v[1] << 16);
         pk.y = v[2] | ((uint32_t)v[3] << 16);
         pk.z = v[4] | ((uint32_t)v[5] << 16);
         pk.w = v[6] | ((uint32_t)v[7] << 16);
-        *(uint4*)(row + p) = pk;
-      } else {
-        for (int c = 0; c < 8 && p + c < N; ++c) row[p + c] = v[c];
+        *(uint4*)(row + p) = pk;     // N is a multiple of 8
       }
+      if (lane == 0) I.row_cnt[q] = 0u;
     }
-    if (lane == 0) I.row_cnt[q] = 0u;
+    __syncthreads();
   }
-  __syncthreads();
-  if (lds_counts) {
+  // the block's counts into the instance totals (integer sums: order-independent)
+  if (lds_counts)
     for (int v = t; v <= R; v += 256)
       if (lcount[v]) atomicAdd((unsigned long long*)&I.counts[v], (unsigned long long)lcount[v]);
-  }
   if (t == 0 && contested_blk) atomicAdd((unsigned long long*)&I.st->contested, contested_blk);
 }
-
-// host launchers --------------------------------------------------------------
 
 void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u) {

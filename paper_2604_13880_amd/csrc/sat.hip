@@ -27,21 +27,84 @@
 
 namespace cgk {
 
-template <bool DENSE>
-__device__ __forceinline__ float dens_at(const Inst& I, const float* lut_s, bool lut_lds, int p, int q) {
+// Stage the densities of rows [y0, y0+TH) x columns [xs, xs+W) into LDS
+// (zero outside the texture).  W and xs are multiples of 8 and N is a
+// power of two >= 16, so every 8-wide chunk is entirely inside or outside;
+// each chunk is one 16-byte (labels) or two 16-byte (density) loads.
+template <bool DENSE, int TH, int W, int NT>
+__device__ __forceinline__ void stage_density(const Inst& I, const float* lut_s, bool lut_lds, int xs,
+                                              int y0, float (*ds)[W]) {
+  constexpr int CH = W / 8;
   const int N = I.N;
-  if (p < 0 || p >= N || q < 0 || q >= N) return 0.f;
-  if (DENSE) return I.density[(int64_t)q * N + p];
-  const int lab = I.labels[(int64_t)q * N + p];
-  if (lab >= I.n_lut) return 0.f;  // labels outside the LUT carry no mass
-  return lut_lds ? lut_s[lab] : I.lut[lab];
+  for (int c = threadIdx.x; c < TH * CH; c += NT) {
+    const int r = c / CH, k = c - r * CH;
+    const int q = y0 + r, p = xs + 8 * k;
+    float v[8];
+    if (q < N && p >= 0 && p < N) {
+      const int64_t at = (int64_t)q * N + p;
+      if (DENSE) {
+        const float4 a = *(const float4*)(I.density + at);
+        const float4 b = *(const float4*)(I.density + at + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+      } else {
+        const uint4 L = *(const uint4*)(I.labels + at);
+        const uint32_t w4[4] = {L.x, L.y, L.z, L.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int lab = (int)((w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          v[e] = lab < I.n_lut ? (lut_lds ? lut_s[lab] : I.lut[lab]) : 0.f;  // labels outside the LUT carry no mass
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ds[r][8 * k + e] = v[e];
+  }
 }
 
-template <typename A>
-__device__ __forceinline__ A mid(const A& a, const A& b) {
-  A s = a;
-  acc_addv(s, b);
-  return acc_half(s);
+constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of the tile)
+
+// Row prefix sums of one sub-band: M[rr][c] = base + (L(c) - L(c0)) + d(c)/2
+// where L is the exclusive prefix of the row over the staged columns and
+// c0 the column where the carried base applies (0 for a tile without halo).
+template <typename A, int W, int NW>
+__device__ __forceinline__ void sub_band_scan(const float (*ds)[W], A (*Ms)[W], const A* base, int c0,
+                                              A* rowtot) {
+  constexpr int E = W / 64 + 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int rr = w; rr < kSub_Rows; rr += NW) {
+    float dv[E];
+    A loc;
+    acc_zero(loc);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int c = lane * E + e;
+      dv[e] = c < W ? ds[rr][c] : 0.f;
+      acc_add(loc, dv[e]);
+    }
+    A run = wave_exclusive_scan(loc, lane);
+    A lv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      lv[e] = run;
+      acc_add(run, dv[e]);
+    }
+    const A l0 = shfl_acc(lv[c0 % E], c0 / E);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int c = lane * E + e;
+      if (c < W) {
+        A v = base[rr];
+        acc_addv(v, acc_sub(lv[e], l0));
+        acc_add(v, 0.5f * dv[e]);
+        Ms[rr][c] = v;
+      }
+    }
+    if (rowtot && lane == 63) rowtot[rr] = run;   // local row total (c0 = 0, base 0)
+  }
 }
 
 template <int P, int TW, int TH, bool DENSE>
@@ -51,12 +114,15 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  constexpr int NW = TW / 64, E = TW / 64, D = TW + TH - 1;
-  __shared__ A Rs[TH][TW + 1];
+  constexpr int NW = TW / 64, D = TW + TH - 1, SB = kSub_Rows;
+  __shared__ float ds[SB][TW];
+  __shared__ A Ms[SB][TW];
+  __shared__ A rt[SB];
+  __shared__ A zero4[SB];
   __shared__ float lut_s[kLutLds];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int tile = (int)(b - B.off_tiles[k]);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
@@ -64,56 +130,58 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
   if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  __syncthreads();
-  for (int r = w; r < TH; r += NW) {
-    const int q = y0 + r;
-    float dv[E];
-    A loc;
-    acc_zero(loc);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      dv[e] = dens_at<DENSE>(I, lut_s, lut_lds, x0 + lane * E + e, q);
-      acc_add(loc, dv[e]);
-    }
-    A run = wave_exclusive_scan(loc, lane);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      Rs[r][lane * E + e] = run;
-      acc_add(run, dv[e]);
-    }
-    if (lane == 63) Rs[r][TW] = run;
-  }
-  __syncthreads();
+  if (t < SB) acc_zero(zero4[t]);
   Cy* agg = (Cy*)I.agg;
   const int64_t tid = (int64_t)ty * L.ntx + tx;
-  for (int r = t; r < TH; r += TW) agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(Rs[r][TW]);
-  {
-    A s;
-    acc_zero(s);
-    for (int r = 0; r < TH; ++r) acc_addv(s, Rs[r][t + 1]);
-    agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(s);
-    if (t == 0) agg[L.colsum + tid * (TW + 1)] = (Cy)0;
-  }
-  for (int c = t; c < D; c += TW) {
-    A sa, sb;
-    acc_zero(sa);
-    acc_zero(sb);
-    for (int r = 0; r < TH; ++r) {
-      const int ca = c - r;                 // anti-diagonal u = x0+y0+c meets row y0+r at column x0+ca
-      if (ca >= TW) acc_addv(sa, Rs[r][TW]);
-      else if (ca >= 0) acc_addv(sa, mid(Rs[r][ca], Rs[r][ca + 1]));
-      const int cb = c + r - TH + 1;        // diagonal v = x0-y0-TH+1+c meets it at column x0+cb
-      if (cb >= TW) acc_addv(sb, Rs[r][TW]);
-      else if (cb >= 0) acc_addv(sb, mid(Rs[r][cb], Rs[r][cb + 1]));
+  // per-thread partial aggregates: column prefix (c = t+1), two anti-diagonal
+  // and two diagonal cumulative masses (c = t, t+TW), the tile total
+  A col, sa0, sa1, sb0, sb1, tot;
+  acc_zero(col); acc_zero(sa0); acc_zero(sa1); acc_zero(sb0); acc_zero(sb1); acc_zero(tot);
+  const int c1 = t + TW;
+  const bool has1 = c1 < D;
+  for (int r0 = 0; r0 < TH; r0 += SB) {
+    __syncthreads();
+    stage_density<DENSE, SB, TW, TW>(I, lut_s, lut_lds, x0, y0 + r0, ds);
+    __syncthreads();
+    sub_band_scan<A, TW, NW>(ds, Ms, zero4, 0, rt);
+    __syncthreads();
+    for (int rr = 0; rr < SB; ++rr) {
+      const int r = r0 + rr;
+      const A rowT = rt[rr];
+      if (t == 0) {
+        agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rowT);
+        acc_addv(tot, rowT);
+      }
+      // R(x0 + t + 1) = M(t+1) - d(t+1)/2, or the row total at the right edge
+      if (t + 1 < TW) {
+        A v = Ms[rr][t + 1];
+        acc_add(v, -0.5f * ds[rr][t + 1]);
+        acc_addv(col, v);
+      } else {
+        acc_addv(col, rowT);
+      }
+      int ca = t - r;              // anti-diagonal u = x0+y0+c meets row y0+r at column x0+c-r
+      if (ca >= TW) acc_addv(sa0, rowT); else if (ca >= 0) acc_addv(sa0, Ms[rr][ca]);
+      int cb = t + r - TH + 1;     // diagonal v = x0-y0-TH+1+c meets it at column x0+c+r-TH+1
+      if (cb >= TW) acc_addv(sb0, rowT); else if (cb >= 0) acc_addv(sb0, Ms[rr][cb]);
+      if (has1) {
+        ca = c1 - r;
+        if (ca >= TW) acc_addv(sa1, rowT); else if (ca >= 0) acc_addv(sa1, Ms[rr][ca]);
+        cb = c1 + r - TH + 1;
+        if (cb >= TW) acc_addv(sb1, rowT); else if (cb >= 0) acc_addv(sb1, Ms[rr][cb]);
+      }
     }
-    agg[L.cdfA + tid * D + c] = to_carry(sa);
-    agg[L.cdfB + tid * D + c] = to_carry(sb);
   }
+  agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(col);
   if (t == 0) {
-    A s;
-    acc_zero(s);
-    for (int r = 0; r < TH; ++r) acc_addv(s, Rs[r][TW]);
-    agg[L.tileTot + tid] = to_carry(s);
+    agg[L.colsum + tid * (TW + 1)] = (Cy)0;
+    agg[L.tileTot + tid] = to_carry(tot);
+  }
+  agg[L.cdfA + tid * D + t] = to_carry(sa0);
+  agg[L.cdfB + tid * D + t] = to_carry(sb0);
+  if (has1) {
+    agg[L.cdfA + tid * D + c1] = to_carry(sa1);
+    agg[L.cdfB + tid * D + c1] = to_carry(sb1);
   }
 }
 
@@ -121,7 +189,7 @@ template <int P, int TW, int TH>
 __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
   typedef typename PT<P>::carry Cy;
   const int k = find_inst(B.off_carry1, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int64_t idx = (int64_t)(blockIdx.x - B.off_carry1[k]) * 256 + threadIdx.x;
@@ -143,17 +211,11 @@ __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
       run += v;
     }
     agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx] = run;
-  } else if (idx == L.NY + L.nty) {
-    Cy C = 0;
-    for (int ty = 0; ty < L.nty; ++ty) {
-      Cy band = 0;
-      for (int tx = 0; tx < L.ntx; ++tx) band += agg[L.tileTot + (int64_t)ty * L.ntx + tx];
-      C += band;
-    }
-    agg[L.Cval] = C;
   }
 }
 
+// Mass of tile row ty on the anti-diagonal side u (tiles fully below u give
+// their totals through the tile-row prefix, at most two tiles are cut).
 template <int TW, int TH, typename Cy>
 __device__ __forceinline__ Cy band_a(const Cy* agg, const SatLayout& L, int ty, int64_t u) {
   constexpr int D = TW + TH - 1;
@@ -162,9 +224,10 @@ __device__ __forceinline__ Cy band_a(const Cy* agg, const SatLayout& L, int ty, 
   klo = klo < 0 ? 0 : (klo > L.ntx ? L.ntx : klo);
   int64_t khi = floordiv(u - y0, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
+  const int64_t base = L.cdfA + (int64_t)ty * L.ntx * D;
   Cy s = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
-  for (int64_t tx = klo; tx <= khi; ++tx)
-    s += agg[L.cdfA + ((int64_t)ty * L.ntx + tx) * D + (u - tx * TW - y0)];
+  if (klo <= khi) s += agg[base + klo * D + (u - klo * TW - y0)];
+  if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (u - (klo + 1) * TW - y0)];
   return s;
 }
 
@@ -176,62 +239,91 @@ __device__ __forceinline__ Cy band_b(const Cy* agg, const SatLayout& L, int ty, 
   klo = klo < 0 ? 0 : (klo > L.ntx ? L.ntx : klo);
   int64_t khi = floordiv(v + y0 + TH - 1, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
+  const int64_t base = L.cdfB + (int64_t)ty * L.ntx * D;
   Cy s = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
-  for (int64_t tx = klo; tx <= khi; ++tx)
-    s += agg[L.cdfB + ((int64_t)ty * L.ntx + tx) * D + (v - tx * TW + y0 + TH - 1)];
+  if (klo <= khi) s += agg[base + klo * D + (v - klo * TW + y0 + TH - 1)];
+  if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (v - (klo + 1) * TW + y0 + TH - 1)];
   return s;
 }
 
+// Carries entering every tile row: for each index (node column i for S,
+// anti-diagonal u for TA, diagonal v for TB) an exclusive scan over the tile
+// rows of the band values.  A block holds IPB indices x CH chunks of
+// kCarryRows tile rows; chunk sums are joined by an LDS scan.
 template <int P, int TW, int TH>
 __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
   const int k = find_inst(B.off_carry2, B.n, blockIdx.x);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
+  __shared__ Cy part[256];
+  __shared__ Cy partC[256];
   const SatLayout L = sat_layout(I.N, TW, TH);
-  const int N = I.N;
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_carry2[k]) * 256 + threadIdx.x;
+  const int N = I.N, nty = L.nty;
+  const int CH = L.carry_ch, IPB = 256 / CH;
+  const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
+  const int64_t idx = (int64_t)(blockIdx.x - B.off_carry2[k]) * IPB + j;
   const Cy* agg = (const Cy*)I.agg;
   Cy* carry = (Cy*)I.carry;
   const int64_t nS = L.NX + 1;
-  if (idx < nS) {
-    const int i = (int)idx;
-    int tx = i / TW;
-    if (tx > L.ntx - 1) tx = L.ntx - 1;
-    const int c = i - tx * TW;
-    Cy run = 0;
-#pragma unroll 4
-    for (int ty = 0; ty < L.nty; ++ty) {
-      const Cy band = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx] +
-                      agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + c];
-      carry[L.Stop + (int64_t)ty * nS + i] = run;
-      run += band;
+  const int seg = idx < nS ? 0 : (idx < nS + L.LA ? 1 : (idx < nS + L.LA + L.LB ? 2 : 3));
+  const int ty0 = ch * kCarryRows;
+  Cy band[kCarryRows], tot[kCarryRows];
+  Cy sum = 0, sumC = 0;
+#pragma unroll
+  for (int d = 0; d < kCarryRows; ++d) {
+    const int ty = ty0 + d;
+    Cy v = 0, w = 0;
+    if (ty < nty) {
+      if (seg == 0) {
+        const int i = (int)idx;
+        int tx = i / TW;
+        if (tx > L.ntx - 1) tx = L.ntx - 1;
+        v = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx] +
+            agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + (i - tx * TW)];
+      } else if (seg == 1) {
+        v = band_a<TW, TH>(agg, L, ty, idx - nS - 1);
+      } else if (seg == 2) {
+        v = band_b<TW, TH>(agg, L, ty, idx - nS - L.LA - L.NY);
+        w = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx];
+      }
     }
-  } else if (idx < nS + L.LA) {
-    const int64_t a = idx - nS;
-    const int64_t u = a - 1;
-    Cy run = 0;
-#pragma unroll 4
-    for (int ty = 0; ty < L.nty; ++ty) {
-      const Cy band = band_a<TW, TH>(agg, L, ty, u);
-      carry[L.TAc + (int64_t)ty * L.LA + a] = run;
-      run += band;
+    band[d] = v;
+    tot[d] = w;
+    sum += v;
+    sumC += w;
+  }
+  part[t] = sum;
+  partC[t] = sumC;
+  __syncthreads();
+  if (seg == 3) return;
+  Cy run = 0, C = 0;
+  for (int cc = 0; cc < ch; ++cc) {
+    run += part[cc * IPB + j];
+    C += partC[cc * IPB + j];
+  }
+#pragma unroll
+  for (int d = 0; d < kCarryRows; ++d) {
+    const int ty = ty0 + d;
+    if (ty < nty) {
+      if (seg == 0) carry[L.Stop + (int64_t)ty * nS + idx] = run;
+      else if (seg == 1) carry[L.TAc + (int64_t)ty * L.LA + (idx - nS)] = run;
+      else carry[L.TBc + (int64_t)ty * L.LB + (idx - nS - L.LA)] = run;
+      run += band[d];
+      C += tot[d];        // the total in the order the diagonal sums use
     }
-    carry[L.TAc + (int64_t)L.nty * L.LA + a] = run;
-    if (a <= 2 * N) ((St*)I.HA)[a] = (St)run;          // HA(s) = TA(s-1, N), s = a
-  } else if (idx < nS + L.LA + L.LB) {
-    const int64_t bi = idx - nS - L.LA;
-    const int64_t v = bi - L.NY;
-    Cy run = 0;
-#pragma unroll 4
-    for (int ty = 0; ty < L.nty; ++ty) {
-      const Cy band = band_b<TW, TH>(agg, L, ty, v);
-      carry[L.TBc + (int64_t)ty * L.LB + bi] = run;
-      run += band;
+  }
+  if (ch == CH - 1) {
+    if (seg == 1) {
+      const int64_t a = idx - nS;
+      carry[L.TAc + (int64_t)nty * L.LA + a] = run;
+      if (a <= 2 * N) ((St*)I.HA)[a] = (St)run;                 // HA(s) = TA(s-1, N), s = a
+    } else if (seg == 2) {
+      const int64_t bi = idx - nS - L.LA, v = bi - L.NY;
+      carry[L.TBc + (int64_t)nty * L.LB + bi] = run;
+      if (v >= -N && v <= N) ((St*)I.HB)[N - v] = (St)(C - run);  // HB(r) = C - TB(-r, N)
     }
-    carry[L.TBc + (int64_t)L.nty * L.LB + bi] = run;
-    if (v >= -N && v <= N) ((St*)I.HB)[N - v] = (St)(agg[L.Cval] - run);   // HB(r) = C - TB(-r, N)
   }
 }
 
@@ -240,64 +332,29 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
-  constexpr int NW = TW / 64;
+  constexpr int NW = TW / 64, SB = kSub_Rows;
   constexpr int XW = TW + 2 * TH;          // columns x0-TH .. x0+TW+TH-1
-  constexpr int E = XW / 64 + 1;            // lanes cover c = 0..XW inclusive
   constexpr int NSL = TW + TH + 1;         // anti-diagonal / diagonal slots
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
-  const Inst& I = B.inst[k];
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  __shared__ A Rs[TH][XW + 1];
-  __shared__ A ta[2][NSL];
-  __shared__ A tb[2][NSL];
+  __shared__ float ds[SB][XW];
+  __shared__ A Ms[SB][XW];
+  __shared__ A taB[SB][NSL];
+  __shared__ A tbB[SB][NSL];
+  __shared__ A rc_s[TH];
   __shared__ float lut_s[kLutLds];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x;
   const int N = I.N;
   const SatLayout L = sat_layout(N, TW, TH);
   const int tile = (int)(b - B.off_tiles[k]);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
-  if (lut_lds)
-    for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  __syncthreads();
   const Cy* agg = (const Cy*)I.agg;
   const Cy* carry = (const Cy*)I.carry;
-  // row prefix sums over the tile and its halo: R(x0-TH+c, q) for c in [0, XW]
-  for (int r = w; r < TH; r += NW) {
-    const int q = y0 + r;
-    float dv[E];
-    A loc;
-    acc_zero(loc);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int c = lane * E + e;
-      dv[e] = c < XW ? dens_at<DENSE>(I, lut_s, lut_lds, x0 - TH + c, q) : 0.f;
-      acc_add(loc, dv[e]);
-    }
-    A run = wave_exclusive_scan(loc, lane);
-    A lv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      lv[e] = run;
-      acc_add(run, dv[e]);
-    }
-    // R(c) = R(x0, q) + (L(c) - L(TH)) keeps R exact at the tile's left edge
-    const A lth = shfl_acc(lv[TH % E], TH / E);
-    A rc;
-    from_carry(rc, agg[L.RC + (int64_t)tx * L.NY + q]);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int c = lane * E + e;
-      if (c <= XW) {
-        A v = rc;
-        acc_addv(v, acc_sub(lv[e], lth));
-        Rs[r][c] = v;
-      }
-    }
-  }
   // carries entering the tile
   A sacc, saccN;
   from_carry(sacc, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
@@ -316,6 +373,9 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     acc_zero(ra[1]);
     acc_zero(rb[1]);
   }
+  for (int r = t; r < TH; r += TW) from_carry(rc_s[r], agg[L.RC + (int64_t)tx * L.NY + y0 + r]);
+  if (lut_lds)
+    for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
   St* S = (St*)I.S;
   St* T = (St*)I.T;
   const int64_t pitch = I.pitch;
@@ -330,38 +390,41 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       T[N] = (St)0;
     }
   }
-  __syncthreads();
-  for (int r = 0; r < TH; ++r) {
-    const int j = y0 + r + 1;
-    acc_addv(sacc, Rs[r][t + TH]);
-    if (extra) acc_addv(saccN, Rs[r][TW + TH]);
-    {
-      const int ca = t + TH - 1 - r;         // anti-diagonal slot t meets row y0+r here
-      acc_addv(ra[0], mid(Rs[r][ca], Rs[r][ca + 1]));
-      const int cb = t + r;                  // diagonal slot t
-      acc_addv(rb[0], mid(Rs[r][cb], Rs[r][cb + 1]));
-      ta[r & 1][t] = ra[0];
-      tb[r & 1][t] = rb[0];
-    }
-    if (has1) {
-      const int ca = s1 + TH - 1 - r;
-      acc_addv(ra[1], mid(Rs[r][ca], Rs[r][ca + 1]));
-      const int cb = s1 + r;
-      acc_addv(rb[1], mid(Rs[r][cb], Rs[r][cb + 1]));
-      ta[r & 1][s1] = ra[1];
-      tb[r & 1][s1] = rb[1];
+  for (int r0 = 0; r0 < TH; r0 += SB) {
+    __syncthreads();
+    stage_density<DENSE, SB, XW, TW>(I, lut_s, lut_lds, x0 - TH, y0 + r0, ds);
+    __syncthreads();
+    // centre prefix over the tile and its halo, exact at the tile's left edge
+    sub_band_scan<A, XW, NW>(ds, Ms, rc_s + r0, TH, (A*)nullptr);
+    __syncthreads();
+    for (int rr = 0; rr < SB; ++rr) {
+      const int r = r0 + rr, j = y0 + r + 1;
+      A v = Ms[rr][t + TH];                  // R(x0+t) = M - d/2
+      acc_add(v, -0.5f * ds[rr][t + TH]);
+      acc_addv(sacc, v);
+      if (extra) acc_addv(saccN, Ms[rr][TW + TH]);   // column N lies outside: R = M there
+      if (j <= N) {
+        if (i <= N) S[(int64_t)j * pitch + i] = to_store(sacc);
+        if (extra) S[(int64_t)j * pitch + N] = to_store(saccN);
+      }
+      acc_addv(ra[0], Ms[rr][t + TH - 1 - r]);   // anti-diagonal slot t meets row y0+r here
+      acc_addv(rb[0], Ms[rr][t + r]);            // diagonal slot t
+      taB[rr][t] = ra[0];
+      tbB[rr][t] = rb[0];
+      if (has1) {
+        acc_addv(ra[1], Ms[rr][s1 + TH - 1 - r]);
+        acc_addv(rb[1], Ms[rr][s1 + r]);
+        taB[rr][s1] = ra[1];
+        tbB[rr][s1] = rb[1];
+      }
     }
     __syncthreads();
-    if (j <= N) {
+    for (int rr = 0; rr < SB; ++rr) {
+      const int r = r0 + rr, j = y0 + r + 1;
+      if (j > N) break;
       const int64_t row = (int64_t)j * pitch;
-      if (i <= N) {
-        S[row + i] = to_store(sacc);
-        T[row + i] = to_store(acc_sub(ta[r & 1][t + r + 1], tb[r & 1][t + TH - 1 - r]));
-      }
-      if (extra) {
-        S[row + N] = to_store(saccN);
-        T[row + N] = to_store(acc_sub(ta[r & 1][TW + r + 1], tb[r & 1][TW + TH - 1 - r]));
-      }
+      if (i <= N) T[row + i] = to_store(acc_sub(taB[rr][t + r + 1], tbB[rr][t + TH - 1 - r]));
+      if (extra) T[row + N] = to_store(acc_sub(taB[rr][TW + r + 1], tbB[rr][TW + TH - 1 - r]));
     }
   }
 }
@@ -395,6 +458,7 @@ static bool launch_sat_p(const Batch& B, int tw, int th, bool dense, int64_t til
   else if (tw == 128 && th == 16) launch_sat_t<P, 128, 16>(B, dense, tiles, c1, c2, s, h, u);
   else if (tw == 128 && th == 32) launch_sat_t<P, 128, 32>(B, dense, tiles, c1, c2, s, h, u);
   else if (tw == 256 && th == 32) launch_sat_t<P, 256, 32>(B, dense, tiles, c1, c2, s, h, u);
+  else if (tw == 256 && th == 64) launch_sat_t<P, 256, 64>(B, dense, tiles, c1, c2, s, h, u);
   else return false;
   return true;
 }
@@ -404,12 +468,13 @@ bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, int64_t ti
   if (prec == CG_F32) return launch_sat_p<CG_F32>(B, tw, th, dense, tiles, c1, c2, s, h, u);
   if (prec == CG_COMP) return launch_sat_p<CG_COMP>(B, tw, th, dense, tiles, c1, c2, s, h, u);
   if (prec == CG_F64) return launch_sat_p<CG_F64>(B, tw, th, dense, tiles, c1, c2, s, h, u);
+  if (prec == CG_F64ACC) return launch_sat_p<CG_F64ACC>(B, tw, th, dense, tiles, c1, c2, s, h, u);
   return false;
 }
 
 bool sat_shape_supported(int tw, int th) {
   return (tw == 64 && th == 16) || (tw == 128 && th == 16) || (tw == 128 && th == 32) ||
-         (tw == 256 && th == 32);
+         (tw == 256 && th == 32) || (tw == 256 && th == 64);
 }
 
 }  // namespace cgk

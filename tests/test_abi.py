@@ -48,7 +48,8 @@ def test_inim_size_and_argument_checks_without_gpu(lib):
     assert f(1000, 0, C.byref(p), C.byref(tb), C.byref(mb)) == -1      # not a power of two
     assert f(8, 0, None, None, None) == -1                               # below 16
     assert f(16384, 0, None, None, None) == -1                           # above 8192
-    assert f(64, 3, None, None, None) == -1                              # bad precision
+    assert f(64, 3, None, None, None) == 0                               # double accumulation, float tables
+    assert f(64, 4, None, None, None) == -1                              # bad precision
 
 
 def test_create_fails_cleanly_without_gpu(lib):

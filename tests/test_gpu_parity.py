@@ -13,7 +13,8 @@ from synth import lognormal_values, square_grid_map, voronoi_map
 pytestmark = pytest.mark.gpu
 
 # |S - S_oracle| / C and |T - T_oracle| / C bounds per accumulation mode
-INIM_TOL = {0: 3e-6, 1: 3e-7, 2: 1e-12}
+INIM_TOL = {0: 3e-6, 1: 3e-7, 2: 1e-12, 3: 3e-7}
+SHAPES = [(64, 16), (128, 16), (128, 32), (256, 32), (256, 64)]
 
 
 def say(*a):
@@ -112,7 +113,7 @@ def _cmp_inim(im, ref, prec, N):
 
 
 @pytest.mark.parametrize("N", [16, 32, 64, 256, 1024, 2048])
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_integral_image_dense(ctx, N, prec):
     d = np.random.default_rng(N + 17 * prec).lognormal(0, 1, (N, N)).astype(np.float32)
     say("inim dense", N, prec)
@@ -121,7 +122,26 @@ def test_integral_image_dense(ctx, N, prec):
     _cmp_inim(im, ref, prec, N)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("N", [16, 128, 1024])
+def test_integral_image_every_tile_shape(ctx, shape, N):
+    d = np.random.default_rng(N + shape[0] + shape[1]).lognormal(0, 1, (N, N)).astype(np.float32)
+    ctx.set_tile_shape(N, 3, N * N, *shape)
+    say("inim shape", shape, "N", N)
+    im = ctx.integral_image(N, density=d, precision=3)
+    _cmp_inim(im, oc.integral_images(d.astype(np.float64)), 3, N)
+
+
+def test_autotune_picks_a_supported_shape(ctx, tmp_path):
+    cache = str(tmp_path / "tiles.txt")
+    shape = ctx.autotune(512, 3, 2, cache)
+    assert tuple(shape) in SHAPES
+    again = ctx.autotune(512, 3, 2, cache)      # read back from the cache file
+    assert tuple(again) == tuple(shape)
+    assert len(open(cache).read().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_integral_image_labels(ctx, prec):
     m = voronoi_map(2000, 100, 50000, fractal=True)
     N = 1024
@@ -159,7 +179,7 @@ def test_map_points_from_oracle_tables(ctx, N):
     assert err <= 1.2e-7      # float32 rounding of the result (positions in [0, 1])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_one_iteration_matches_oracle(ctx, prec):
     # rasterise, density, integral images and move on the GPU for one step
     import torch
@@ -225,7 +245,7 @@ def test_per_iteration_parity_config1(ctx):
     say("per-iteration worst", worst)
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_end_to_end_config1(ctx, prec):
     """20 iterations on the GPU against the FP64 oracle with a float32
     state: positions within 1e-5 of the domain width."""
