@@ -38,8 +38,10 @@ WORKLOADS = {
                          "iterate to max area error < 1% or the stopping rule, compensated FP32 integral images"),
     "config1": dict(seed=1000, R=32, n=2000, fractal=False, sigma=1.0, N=256, precision=1, fixed=20,
                     desc="32 Voronoi regions (~2k vertices), lognormal sigma 1, 256^2 texture, 20 iterations"),
+    "config3": dict(seed=3000, R=200, n=200000, fractal=True, sigma=1.0, N=2048, precision=3, T=64,
+                    desc="200 fractal Voronoi regions (~200k vertices), 2048^2, 64 time steps of a geometric "
+                         "random walk (step sigma 0.1), all steps batched (direct), FP64-accumulated integral images"),
 }
-
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -64,6 +66,55 @@ def cpu_baseline(m, values, N, gpu_iters, sample_iters):
                        f"per-iteration time x {gpu_iters} iterations of the GPU run")
 
 
+def precision_table(ctx, B, m, values, N):
+    """Max |S - S64| / C and |T - T64| / C of the float-stored modes against
+    double accumulation and storage, on the map's density texture."""
+    import torch
+    gm = ctx.map_from(m)
+    lab, cnt, _ = ctx.rasterize(gm, torch.from_numpy(m.xy32()).cuda(), N)
+    c = cnt.double().cpu().numpy()
+    lut = np.zeros(m.n_regions + 1, np.float32)
+    lut[1:] = np.where(c[1:] > 0, values / np.maximum(c[1:], 1), 0)
+    lut[0] = values.sum() / max(c[1:].sum(), 1)
+    lut /= lut.mean()
+    lutt = torch.from_numpy(lut).cuda()
+    ref = ctx.integral_image(N, labels=lab, lut=lutt, precision=B.F64)
+    C = float(ref.S[N, N])
+    out = {}
+    for name, prec in (("F32", B.F32), ("COMP", B.COMP), ("F64ACC", B.F64ACC)):
+        im = ctx.integral_image(N, labels=lab, lut=lutt, precision=prec)
+        eS = float((im.S[:, : N + 1].double() - ref.S[:, : N + 1]).abs().max()) / C
+        eT = float((im.T[:, : N + 1].double() - ref.T[:, : N + 1]).abs().max()) / C
+        out[name] = {"S_rel": eS, "T_rel": eT}
+    return out
+
+
+def run_series(a, w, B, ctx, torch):
+    """Config 3: every step of a 64-step value series as one direct batch."""
+    from synth import random_walk_series, voronoi_map
+    log("config3: generating map")
+    m = voronoi_map(w["seed"], w["R"], w["n"], fractal=True)
+    S = random_walk_series(w["seed"], w["R"], w["T"], sigma0=w["sigma"]).astype(np.float32)
+    N = w["N"]
+    gm = ctx.map_from(m)
+    shape = ctx.autotune(N, w["precision"], w["T"])
+    desc = dict(map=gm, xy0=torch.from_numpy(m.xy32()).cuda(), N=N, values=torch.from_numpy(S).cuda(),
+                precision=w["precision"], frames=10)
+    ctx.step_series([desc], graph_iters=a.graph_iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        r = ctx.step_series([desc], graph_iters=a.graph_iters)[0]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    iters = r["iters"].astype(np.int64)
+    return dict(workload=w["desc"], ms_per_series=ms, ms_per_cartogram=ms / w["T"],
+                mpx_iter_per_s=float(N * N * iters.sum() / (ms / 1e3) / 1e6),
+                iterations_mean=float(iters.mean()), iterations_max=int(iters.max()),
+                converged=int((r["status"] == 0).sum()), steps=int(w["T"]), tile=list(shape),
+                frames_per_transition=10, precision_vs_f64=precision_table(ctx, B, m, S[0], N))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,8 +126,21 @@ def main():
     ap.add_argument("--graph-iters", type=int, default=-8,
                     help="iterations between convergence polls; negative = eager launches "
                          "(HIP events around the timed stage are only recorded outside graphs)")
-    ap.add_argument("--stage", default="sat_final")
+    ap.add_argument("--stage", default="raster_fill", help="kernel timed with HIP events for the roofline")
+    ap.add_argument("--profile-every", type=int, default=8, help="time one launch of the stage per this many iterations")
+    ap.add_argument("--no-series", action="store_true", help="skip the batched 64-step series (config 3)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
     a = ap.parse_args()
+    if a.copy_probe:
+        import torch
+        x = torch.ones(a.copy_probe * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_copy": x.numel() * 4, "copies": 5}))
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported in this build "
               f"(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -96,6 +160,7 @@ def main():
     xy0 = torch.from_numpy(m.xy32()).cuda()
     vals = torch.from_numpy(values).cuda()
     desc = dict(map=gm, xy0=xy0, N=N, values=vals, precision=w["precision"], fixed_iters=w.get("fixed", 0))
+    tile = ctx.autotune(N, w["precision"], 1)
     torch.cuda.synchronize()
 
     log("warmup", a.warmup)
@@ -103,7 +168,7 @@ def main():
         r = ctx.step_series([desc], graph_iters=a.graph_iters)[0]
     torch.cuda.synchronize()
 
-    ctx.profile_stage(a.stage)
+    ctx.profile_stage(a.stage, a.profile_every)
     log("timed", a.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -129,6 +194,10 @@ def main():
                 frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
                 avg_launch_us=avg_ms * 1e3, launches=stage_n, alg_bytes_per_launch=alg_bytes)
 
+    series = None
+    if not a.no_series and a.workload == "config2":
+        series = run_series(a, WORKLOADS["config3"], B, ctx, torch)
+
     cpu = None
     if not a.no_cpu:
         log("cpu baseline", a.cpu_iters, "iterations")
@@ -137,13 +206,13 @@ def main():
     out = {
         "metric": METRIC, "value": ms_step, "unit": "ms per cartogram", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Voronoi maps)",
         "config": {"workload": w["desc"], "texture": N, "regions": w["R"], "vertices": m.n_vertices,
                    "precision": ["F32", "COMP", "F64"][w["precision"]]},
         "mpx_iter_per_s": mpx, "iterations": iters, "final_xi": xi,
         "status": ["converged", "stalled", "maxiter", "error"][status],
         "reached_tol": status == 0, "ms_per_iteration": ms_step / max(iters, 1),
-        "roofline": roof, "cpu_baseline": cpu,
+        "tile": list(tile), "roofline": roof, "cpu_baseline": cpu, "batched_series": series,
     }
     print(json.dumps(out), flush=True)
 

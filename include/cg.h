@@ -20,8 +20,8 @@
  *     [n][2].  Region ids are 1..R; id 0 is the background.
  *   - Every array argument is DEVICE memory unless its comment says
  *     host.  The library never frees caller memory.
- *   - `stream` is a hipStream_t (NULL = the context's own stream).  All
- *     calls are asynchronous on `stream` unless stated otherwise.
+ *   - `stream` is a hipStream_t (NULL = the HIP null stream).  All calls
+ *     are asynchronous on `stream` unless stated otherwise.
  *   - Every call returns CG_OK or a negative CG_E* code; invalid
  *     arguments are rejected before anything is launched, and
  *     cg_last_error() then describes the problem.  One context per host
@@ -72,8 +72,9 @@ extern "C" {
 typedef struct cg_ctx cg_ctx;
 typedef struct cg_map cg_map;
 
-/* Context: owns a stream, scratch workspaces, the tile-shape table and
- * the autotune cache.  `device` is the HIP device ordinal. */
+/* Context: owns scratch workspaces, the tile-shape table and a private
+ * stream on which cg_step_series captures and replays its graphs (after
+ * the caller's stream).  `device` is the HIP device ordinal. */
 int cg_create(int device, cg_ctx** out);
 int cg_destroy(cg_ctx* ctx);
 /* Text of the last error on this context (never NULL; owned by ctx). */
@@ -196,7 +197,8 @@ typedef struct {
 } cg_series_out;
 
 /* Runs every series in desc[0..n_series); out[k] receives series k.
- * Blocking: returns when all steps have stopped.  Iterations are issued
+ * Blocking: starts after the work already queued on `stream` and
+ * returns when all steps have stopped.  Iterations are issued
  * as captured HIP graphs of `graph_iters` iterations (0: default 8; a
  * negative value launches -graph_iters iterations eagerly, without a graph),
  * with a convergence poll between replays. */
@@ -220,11 +222,13 @@ int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* ca
  * cg_profile_stage selects the stage ("raster_count", "raster_scan",
  * "raster_emit", "raster_fill", "density", "sat_reduce", "sat_carry1",
  * "sat_carry2", "sat_final", "map_points", "areas", "err"; NULL or "" to
- * stop) and resets the totals.  While selected, every iteration's launch
- * of that kernel is bracketed by HIP events recorded on the launch stream
- * (captured into the iteration graph), and cg_profile_read returns the
- * summed milliseconds and the number of launches timed so far. */
-int cg_profile_stage(cg_ctx* ctx, const char* stage);
+ * stop) and resets the totals.  While selected, the launch of that kernel
+ * in one of every `every` iterations is bracketed by HIP events recorded
+ * on the launch stream, and cg_profile_read returns the summed
+ * milliseconds and the number of launches timed so far.  Events are only
+ * recorded when the series runs eagerly (graph_iters < 0): HIP does not
+ * time event records captured into graphs. */
+int cg_profile_stage(cg_ctx* ctx, const char* stage, int32_t every);
 int cg_profile_read(cg_ctx* ctx, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus

@@ -74,7 +74,7 @@ def lib():
             "cg_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, C.POINTER(i32), C.POINTER(i32)]),
             "cg_autotune": (C.c_int, [vp, C.c_int, C.c_int, i32, C.c_char_p]),
             "cg_set_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, i32, i32]),
-            "cg_profile_stage": (C.c_int, [vp, C.c_char_p]),
+            "cg_profile_stage": (C.c_int, [vp, C.c_char_p, i32]),
             "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
@@ -253,8 +253,8 @@ class Context:
         self._check(rc, "cg_region_areas")
         return areas, ex
 
-    def profile_stage(self, stage: str | None):
-        self._check(lib().cg_profile_stage(self.handle, (stage or "").encode()), "cg_profile_stage")
+    def profile_stage(self, stage: str | None, every: int = 1):
+        self._check(lib().cg_profile_stage(self.handle, (stage or "").encode(), int(every)), "cg_profile_stage")
 
     def profile_read(self):
         ms, n = C.c_double(), C.c_int64()

@@ -69,8 +69,9 @@ struct cg_map {
 
 struct cg_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // private stream of the series driver (graph capture)
   hipStream_t last = nullptr;
+  bool last_set = false;
   std::string err;
   std::map<std::string, DevBuf> bufs;
   char* pinned = nullptr;
@@ -80,6 +81,7 @@ struct cg_ctx {
   std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tiles;  // (N, prec, batch px) -> shape
   // per-stage timing of series iterations
   int prof_stage = -1;
+  int prof_every = 1;        // time one launch in every prof_every iterations
   std::vector<hipEvent_t> prof_ev;
   int prof_k = 0;            // iterations recorded per graph replay
   double prof_ms = 0.0;
@@ -102,10 +104,14 @@ int fail(cg_ctx* c, int code, const std::string& msg) {
       return fail(ctx, CG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// The stream a call runs on: the caller's (NULL is the HIP null stream).
+// Scratch buffers are shared between calls, so switching streams first
+// drains the previous one.
 hipStream_t pick_stream(cg_ctx* c, void* s) {
-  hipStream_t st = s ? (hipStream_t)s : c->stream;
-  if (c->last && c->last != st) hipStreamSynchronize(c->last);  // scratch is shared between calls
+  hipStream_t st = (hipStream_t)s;
+  if (c->last_set && c->last != st) hipStreamSynchronize(c->last);
   c->last = st;
+  c->last_set = true;
   return st;
 }
 
@@ -403,7 +409,7 @@ struct HookCtx {
 
 void prof_hook(int stage, int after, void* user) {
   HookCtx* h = (HookCtx*)user;
-  if (stage != h->c->prof_stage) return;
+  if (stage != h->c->prof_stage || h->it % h->c->prof_every != 0) return;
   hipEventRecord(h->c->prof_ev[2 * h->it + after], h->c->prof_stream);
 }
 
@@ -800,8 +806,10 @@ static const char* kStageNames[cgk::ST_COUNT] = {
     "raster_count", "raster_scan", "raster_emit", "raster_fill", "density", "sat_reduce",
     "sat_carry1", "sat_carry2", "sat_final", "map_points", "areas", "err"};
 
-int cg_profile_stage(cg_ctx* c, const char* stage) {
+int cg_profile_stage(cg_ctx* c, const char* stage, int32_t every) {
   if (!c) return CG_EINVAL;
+  if (every < 1) return fail(c, CG_EINVAL, "cg_profile_stage: every must be >= 1");
+  c->prof_every = every;
   c->prof_ms = 0.0;
   c->prof_launches = 0;
   c->prof_failed = 0;
@@ -902,7 +910,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
       break;
     }
     if (prof && launched > 0) {
-      for (int it = 0; it < K; ++it) {
+      for (int it = 0; it < K; it += c->prof_every) {
         float ms = 0.f;
         hipError_t e = hipEventElapsedTime(&ms, c->prof_ev[2 * it], c->prof_ev[2 * it + 1]);
         if (e == hipSuccess) {
@@ -996,7 +1004,17 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
     if ((int64_t)d.map->n_vert + d.n_extra > INT32_MAX) return fail(c, CG_EINVAL, "cg_step_series: too many points");
   }
   hipSetDevice(c->device);
-  hipStream_t st = pick_stream(c, stream);
+  // order after the caller's stream, then run on the private (capturable) stream
+  hipStream_t caller = pick_stream(c, stream);
+  hipStream_t st = c->stream;
+  {
+    hipEvent_t ev;
+    HIP_OK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_OK(c, hipEventRecord(ev, caller));
+    HIP_OK(c, hipStreamWaitEvent(st, ev, 0));
+    HIP_OK(c, hipEventDestroy(ev));
+  }
+  c->last = st;
   for (int prec = CG_F32; prec <= CG_F64ACC; ++prec) {
     // direct steps of every series with this precision: one batch
     std::vector<Spec> specs;

@@ -266,126 +266,150 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
     }
     __syncthreads();
     if (row_ok) {
-      // xor-scan over the sorted crossings, 64 at a time
-      bool exact = !bad;
-      uint32_t carry = 0, ngroups = 0;
-      for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
-        const uint32_t kk = c0 + lane;
-        const bool live = kk < cnt;
-        uint64_t rec = live ? srt[w][kk] : 0ull;
-        const uint32_t p0 = (uint32_t)(rec & 0xFFFFu);
-        const uint32_t ra = (uint32_t)((rec >> 16) & 0xFFFFu), rb = (uint32_t)((rec >> 32) & 0xFFFFu);
-        uint32_t x = live ? (ra ^ rb) : 0u;
+    uint32_t ngroups = 0;
+    if (cnt <= 64) {
+      // one crossing per lane, sorted by p0
+      const bool live = lane < (int)cnt;
+      const uint64_t rec = live ? srt[w][lane] : 0ull;
+      const uint32_t p0 = (uint32_t)(rec & 0xFFFFu);
+      const uint32_t ra = (uint32_t)((rec >> 16) & 0xFFFFu), rb = (uint32_t)((rec >> 32) & 0xFFFFu);
+      const uint32_t pnext = __shfl_down(p0, 1, 64);
+      const bool last = live && (lane + 1 == (int)cnt || pnext != p0);
+      uint32_t x = live ? (ra ^ rb) : 0u;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t y = __shfl_up(x, d, 64);
-          if (lane >= d) x ^= y;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x ^= y;
+      }
+      // the lane ending a group of crossings at one p0 replays that group
+      // on the claim set before it ({xb}, or empty when xb = 0): the xor
+      // labels stay exact iff at most one region claims afterwards
+      bool ok = !bad;
+      if (last) {
+        uint32_t xb = x;
+        int j = lane, members = 0;
+        while (true) {
+          const uint64_t rj = srt[w][j];
+          xb ^= (uint32_t)((rj >> 16) & 0xFFFFu) ^ (uint32_t)((rj >> 32) & 0xFFFFu);
+          ++members;
+          if (j == 0 || (uint32_t)(srt[w][j - 1] & 0xFFFFu) != p0 || members > kSetCap) break;
+          --j;
         }
-        const uint32_t X = x ^ carry;                       // label after this crossing
-        uint32_t Xprev = __shfl_up(X, 1, 64);
-        if (lane == 0) Xprev = carry;
-        const bool last = live && (kk + 1 == cnt || (uint32_t)(srt[w][kk + 1] & 0xFFFFu) != p0);
-        // the lane ending a group of crossings at one p0 replays that group
-        // on the claim set before it ({Xb}, or empty when Xb = 0): the
-        // prefix stays exact iff at most one region claims afterwards
-        bool ok = true;
-        if (last) {
+        if (members > kSetCap) {
+          ok = false;
+        } else {
           Claims cl;
+          cl.cur = (int)xb;
           cl.multi = false;
 #pragma unroll
           for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
-          uint32_t xb = X, j = kk;
-          int members = 0;
-          while (true) {
-            const uint64_t rj = srt[w][j];
-            xb ^= (uint32_t)((rj >> 16) & 0xFFFFu) ^ (uint32_t)((rj >> 32) & 0xFFFFu);
-            ++members;
-            if (j == 0 || (uint32_t)(srt[w][j - 1] & 0xFFFFu) != p0 || members > kSetCap) break;
-            --j;
+          bool over = false;
+          for (int i = j; i <= lane; ++i) {
+            const uint64_t ri = srt[w][i];
+            claims_toggle(cl, (int)((ri >> 16) & 0xFFFFu), over);
+            claims_toggle(cl, (int)((ri >> 32) & 0xFFFFu), over);
           }
-          if (members > kSetCap) {
-            ok = false;
-          } else {
-            cl.cur = (int)xb;
-            bool over = false;
-            for (uint32_t i = j; i <= kk; ++i) {
-              const uint64_t ri = srt[w][i];
-              claims_toggle(cl, (int)((ri >> 16) & 0xFFFFu), over);
-              claims_toggle(cl, (int)((ri >> 32) & 0xFFFFu), over);
-            }
-            int lab, n;
-            claims_label(cl, lab, n);
-            ok = !over && n <= 1 && (uint32_t)lab == X;
-          }
+          int lab, n;
+          claims_label(cl, lab, n);
+          ok = ok && !over && n <= 1 && (uint32_t)lab == x;
         }
-        (void)Xprev;
-        if (__any(!ok)) exact = false;
-        // runs start at every group's last crossing: span 1 + (groups before)
-        const uint64_t lastmask = __ballot(last);
-        const uint32_t before = ngroups + __popcll(lastmask & ((1ull << lane) - 1ull));
-        if (last) {
-          sp_start[w][1 + before] = (uint16_t)p0;
-          sp_lab[w][1 + before] = (uint16_t)X;
-        }
-        ngroups += __popcll(lastmask);
-        carry = __shfl(X, 63, 64);
       }
-      if (exact) {
-        if (lane == 0) {
-          sp_start[w][0] = 0;
-          sp_lab[w][0] = 0;
-        }
-        // run lengths into the counts
-        for (uint32_t g = lane; g <= ngroups; g += 64) {
-          const uint32_t st0 = g == 0 ? 0u : sp_start[w][g];
-          const uint32_t en = g == ngroups ? (uint32_t)N : sp_start[w][g + 1];
-          const uint32_t lab = g == 0 ? 0u : sp_lab[w][g];
-          if (en > st0) {
-            if (lds_counts) atomicAdd(&lcount[lab], en - st0);
-            else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)(en - st0));
+      uint32_t label = x, nclaim = x != 0u;
+      if (__any(!ok)) {
+        // exact claim sets in parallel: for every distinct region of the row,
+        // its parity after crossing k is the parity of the crossings <= k
+        // that toggle it
+        label = 0u;
+        nclaim = 0u;
+        const uint64_t upto = (2ull << lane) - 1ull;
+        for (int j = 0; j < (int)cnt; ++j) {
+          for (int side = 0; side < 2; ++side) {
+            const uint32_t v = (uint32_t)__shfl((int)(side ? rb : ra), j, 64);
+            if (v == 0u) continue;
+            const uint64_t m = __ballot(live && (ra == v || rb == v));
+            if ((int)(__ffsll((long long)m) - 1) < j || (side == 1 && (uint32_t)__shfl((int)ra, j, 64) == v)) continue;
+            if (live && (__popcll(m & upto) & 1)) {
+              ++nclaim;
+              label = max(label, v);
+            }
           }
         }
-      } else if (lane == 0) {
-        // exact walk of the claim set
-        Claims cl;
-        cl.cur = 0;
-        cl.multi = false;
+      }
+      // runs: [0, first p0) is background; every group's last crossing starts one
+      const uint64_t lastmask = __ballot(last);
+      const uint32_t before = __popcll(lastmask & ((1ull << lane) - 1ull));
+      unsigned long long cont = 0;
+      if (last) {
+        sp_start[w][1 + before] = (uint16_t)p0;
+        sp_lab[w][1 + before] = (uint16_t)label;
+        const uint32_t en = lane + 1 == (int)cnt ? (uint32_t)N : pnext;
+        if (en > p0) {
+          if (lds_counts) atomicAdd(&lcount[label], en - p0);
+          else atomicAdd((unsigned long long*)&I.counts[label], (unsigned long long)(en - p0));
+          if (nclaim > 1) cont = en - p0;
+        }
+      }
+      if (lane == 0) {
+        sp_start[w][0] = 0;
+        sp_lab[w][0] = 0;
+        const uint32_t first = cnt ? (uint32_t)(srt[w][0] & 0xFFFFu) : (uint32_t)N;
+        if (first > 0) {
+          if (lds_counts) atomicAdd(&lcount[0], first);
+          else atomicAdd((unsigned long long*)&I.counts[0], (unsigned long long)first);
+        }
+      }
+      for (int d = 32; d >= 1; d >>= 1) cont += __shfl_xor(cont, d, 64);
+      if (lane == 0) {
+        if (cont) {
+          atomicAdd(&contested_blk, cont);
+          atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+        }
+        if (bad) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+      }
+      ngroups = __popcll(lastmask);
+    } else if (lane == 0) {
+      // long rows: exact serial walk of the claim set
+      Claims cl;
+      cl.cur = 0;
+      cl.multi = false;
 #pragma unroll
-        for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
-        bool over = false;
-        uint32_t nsp = 0, prev = 0;
-        unsigned long long cont = 0;
-        for (uint32_t i = 0; i <= cnt; ++i) {
-          uint64_t rec = 0;
-          uint32_t p0 = (uint32_t)N;
-          if (i < cnt) {
-            rec = srt[w][i];
-            p0 = (uint32_t)(rec & 0xFFFFu);
-          }
-          if (p0 > prev || (i == cnt && nsp == 0)) {
-            int lab, n;
-            claims_label(cl, lab, n);
-            sp_start[w][nsp] = (uint16_t)prev;
-            sp_lab[w][nsp] = (uint16_t)lab;
-            ++nsp;
-            const uint32_t len = p0 - prev;
-            if (n > 1) cont += len;
-            if (len) {
-              if (lds_counts) atomicAdd(&lcount[lab], len);
-              else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)len);
-            }
-            prev = p0;
-          }
-          if (i < cnt) {
-            claims_toggle(cl, (int)((rec >> 16) & 0xFFFFu), over);
-            claims_toggle(cl, (int)((rec >> 32) & 0xFFFFu), over);
-          }
+      for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
+      bool over = false;
+      uint32_t nsp = 0, prev = 0;
+      unsigned long long cont = 0;
+      for (uint32_t i = 0; i <= cnt; ++i) {
+        uint64_t rec = 0;
+        uint32_t p0 = (uint32_t)N;
+        if (i < cnt) {
+          rec = srt[w][i];
+          p0 = (uint32_t)(rec & 0xFFFFu);
         }
-        ngroups = nsp - 1;
-        if (cont) atomicAdd(&contested_blk, cont);
-        if (bad || over) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
-        if (cont) atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+        if (p0 > prev || (i == cnt && nsp == 0)) {
+          int lab, n;
+          claims_label(cl, lab, n);
+          sp_start[w][nsp] = (uint16_t)prev;
+          sp_lab[w][nsp] = (uint16_t)lab;
+          ++nsp;
+          const uint32_t len = p0 - prev;
+          if (n > 1) cont += len;
+          if (len) {
+            if (lds_counts) atomicAdd(&lcount[lab], len);
+            else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)len);
+          }
+          prev = p0;
+        }
+        if (i < cnt) {
+          claims_toggle(cl, (int)((rec >> 16) & 0xFFFFu), over);
+          claims_toggle(cl, (int)((rec >> 32) & 0xFFFFu), over);
+        }
       }
+      ngroups = nsp - 1;
+      if (cont) {
+        atomicAdd(&contested_blk, cont);
+        atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+      }
+      if (bad || over) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+    }
       ngroups = __shfl(ngroups, 0, 64);
       // fill: spans 0..ngroups, the last span with start <= p holds pixel p
       const int nsp = (int)ngroups + 1;

@@ -339,3 +339,24 @@ def test_shape_parameter(ctx):
         nxt, r = _run1(ctx, gm, m.xy32(), N, s, prec=2, shape=b)
         want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, s.astype(np.float64), N, b=b)
         assert np.abs(nxt - want).max() <= 1e-6
+
+
+@pytest.mark.parametrize("shape", [(128, 32), (256, 32)])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_integral_image_labels_2048(ctx, prec, shape):
+    """Labels + LUT at 2048^2 (config-3 size) for every accumulation mode."""
+    m = voronoi_map(3000, 200, 200000, fractal=True)
+    N = 2048
+    lab, cnt, _ = oc.rasterize(m.xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, N)
+    s = lognormal_values(3000, 200, 1.0)
+    lut, _ = oc.density_lut(cnt, s)
+    lut32 = (lut / lut.mean()).astype(np.float32)
+    ctx.set_tile_shape(N, prec, N * N, *shape)
+    say("inim labels 2048", prec, shape)
+    im = ctx.integral_image(N, labels=lab, lut=lut32, precision=prec)
+    ref = oc.integral_images(lut32.astype(np.float64)[lab.astype(np.int64)])
+    S = _np(im.S)[:, : N + 1].astype(np.float64)
+    err = np.abs(S - ref.S)
+    j, i = np.unravel_index(np.argmax(err), err.shape)
+    say("  worst S at row", j, "col", i, "err/C", err[j, i] / ref.C)
+    _cmp_inim(im, ref, prec, N)
