@@ -12,13 +12,19 @@ fractal boundaries (~50k vertices), values lognormal(sigma = 1.5), a
 paper's stopping rule ends the run), compensated-FP32 integral images.
 
 Printed: one JSON line (rank 0).  `roofline` times the integral-image
-writer kernel (sat_final) with HIP events captured around every launch
-on its stream inside the timed region; `cpu_baseline` times the FP64
-oracle on a bounded sample of the same workload on the host cores.
+writer kernel (sat_final, the largest HBM writer and the longest kernel
+of an iteration) with HIP events recorded on its own stream around one
+launch in every `--profile-every` iterations of the timed region;
+`traffic` is the HBM byte count per launch of the same kernel from the
+rocprofv3 counter summary under profiles/ (scaled by a copy kernel of
+known size), reported only while the kernel source still matches the
+hash recorded with the counters.  `cpu_baseline` times the FP64 oracle
+on a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,6 +48,68 @@ WORKLOADS = {
                     desc="200 fractal Voronoi regions (~200k vertices), 2048^2, 64 time steps of a geometric "
                          "random walk (step sigma 0.1), all steps batched (direct), FP64-accumulated integral images"),
 }
+
+STORE_BYTES = {0: 4, 1: 4, 2: 8, 3: 4}  # stored table entry per precision (F32, COMP, F64, F64ACC)
+PREC_NAMES = ["F32", "COMP", "F64", "F64ACC"]
+KERNEL_SOURCES = {
+    "sat_final": ["paper_2604_13880_amd/csrc/sat.hip", "paper_2604_13880_amd/csrc/cg_dev.h"],
+    "sat_reduce": ["paper_2604_13880_amd/csrc/sat.hip", "paper_2604_13880_amd/csrc/cg_dev.h"],
+    "raster_fill": ["paper_2604_13880_amd/csrc/raster.hip", "paper_2604_13880_amd/csrc/cg_dev.h"],
+    "map_points": ["paper_2604_13880_amd/csrc/mapping.hip", "paper_2604_13880_amd/csrc/cg_dev.h"],
+}
+
+
+def alg_bytes(stage, N, prec, n_pts):
+    """Bytes one launch of `stage` must move for one N x N instance:
+    what the method reads and writes, not what the kernel happens to."""
+    b = STORE_BYTES[prec]
+    if stage == "sat_final":    # labels read + S and T written, (N+1)^2 entries each
+        return 2 * N * N + 2 * (N + 1) ** 2 * b
+    if stage == "sat_reduce":   # labels read
+        return 2 * N * N
+    if stage == "raster_fill":  # labels written
+        return 2 * N * N
+    if stage == "map_points":   # positions in and out + 4 corner nodes x (S, T) gathered per point
+        return n_pts * (16 + 8 * b)
+    raise ValueError(f"no algorithmic byte count for stage {stage}")
+
+
+def sources_hash(stage):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(stage, []):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(stage, workload):
+    """HBM bytes per launch from profiles/<kernel>_<workload>_counters.txt,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != sources_hash(stage):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(stage, ms, n, N, prec, n_pts, instances, workload):
+    per = alg_bytes(stage, N, prec, n_pts) * instances
+    avg_ms = ms / max(n, 1)
+    ach = per / (avg_ms * 1e-3) / 1e9 if n else None
+    return dict(bound="hbm", kernel=stage, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=(ach / HBM_PEAK_GBS) if ach else None, traffic=counter_traffic(stage, workload),
+                avg_launch_us=avg_ms * 1e3, launches=n, alg_bytes_per_launch=per)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -102,17 +170,21 @@ def run_series(a, w, B, ctx, torch):
                 precision=w["precision"], frames=10)
     ctx.step_series([desc], graph_iters=a.graph_iters)
     torch.cuda.synchronize()
+    ctx.profile_stage(a.stage, a.profile_every)
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(a.series_steps):
         r = ctx.step_series([desc], graph_iters=a.graph_iters)[0]
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    ms = (time.perf_counter() - t0) * 1e3 / a.series_steps
+    stage_ms, stage_n = ctx.profile_read()
+    ctx.profile_stage(None)
     iters = r["iters"].astype(np.int64)
     return dict(workload=w["desc"], ms_per_series=ms, ms_per_cartogram=ms / w["T"],
                 mpx_iter_per_s=float(N * N * iters.sum() / (ms / 1e3) / 1e6),
                 iterations_mean=float(iters.mean()), iterations_max=int(iters.max()),
                 converged=int((r["status"] == 0).sum()), steps=int(w["T"]), tile=list(shape),
-                frames_per_transition=10, precision_vs_f64=precision_table(ctx, B, m, S[0], N))
+                frames_per_transition=10, precision_vs_f64=precision_table(ctx, B, m, S[0], N),
+                roofline=roofline(a.stage, stage_ms, stage_n, N, w["precision"], m.n_vertices, w["T"], "config3"))
 
 
 def main():
@@ -126,9 +198,11 @@ def main():
     ap.add_argument("--graph-iters", type=int, default=-8,
                     help="iterations between convergence polls; negative = eager launches "
                          "(HIP events around the timed stage are only recorded outside graphs)")
-    ap.add_argument("--stage", default="raster_fill", help="kernel timed with HIP events for the roofline")
+    ap.add_argument("--stage", default="sat_final", choices=sorted(KERNEL_SOURCES),
+                    help="kernel timed with HIP events for the roofline")
     ap.add_argument("--profile-every", type=int, default=8, help="time one launch of the stage per this many iterations")
     ap.add_argument("--no-series", action="store_true", help="skip the batched 64-step series (config 3)")
+    ap.add_argument("--series-steps", type=int, default=1, help="timed repetitions of the batched series")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
     a = ap.parse_args()
@@ -184,15 +258,7 @@ def main():
     status = int(r["status"][0])
     mpx = N * N * iters / (ms_step / 1e3) / 1e6
 
-    # roofline of the integral-image writer: algorithmic bytes per launch =
-    # label read (2 B/px) + S and T written (2 tables of (N+1)^2 stored values)
-    store = 8 if w["precision"] == 2 else 4
-    alg_bytes = 2 * N * N + 2 * (N + 1) ** 2 * store
-    avg_ms = stage_ms / max(stage_n, 1)
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if stage_n else None
-    roof = dict(bound="hbm", kernel=a.stage, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
-                avg_launch_us=avg_ms * 1e3, launches=stage_n, alg_bytes_per_launch=alg_bytes)
+    roof = roofline(a.stage, stage_ms, stage_n, N, w["precision"], m.n_vertices, 1, a.workload)
 
     series = None
     if not a.no_series and a.workload == "config2":
@@ -208,7 +274,7 @@ def main():
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Voronoi maps)",
         "config": {"workload": w["desc"], "texture": N, "regions": w["R"], "vertices": m.n_vertices,
-                   "precision": ["F32", "COMP", "F64"][w["precision"]]},
+                   "precision": PREC_NAMES[w["precision"]]},
         "mpx_iter_per_s": mpx, "iterations": iters, "final_xi": xi,
         "status": ["converged", "stalled", "maxiter", "error"][status],
         "reached_tol": status == 0, "ms_per_iteration": ms_step / max(iters, 1),
