@@ -181,7 +181,8 @@ typedef struct {
   int32_t frames;       /* K >= 2: K-1 interpolated frames per transition; 0: none */
   const float* extra;   /* [n_extra][2] tracer points moved along, or NULL */
   int64_t n_extra;
-  const float* init_field; /* warm start: float [2][G+1][G+1] displacement at grid nodes, or NULL */
+  const float* init_field; /* warm start: float [G][G][2] displacement (dx, dy) at the pixel centres
+                              ((i + 1/2)/G, (j + 1/2)/G) of a G x G grid, or NULL; see below */
   int32_t init_G;
 } cg_series_desc;
 
@@ -197,6 +198,14 @@ typedef struct {
 } cg_series_out;
 
 /* Runs every series in desc[0..n_series); out[k] receives series k.
+ * Warm start: with init_field, the starting positions (of the first step
+ * in cumulative mode, of every step in direct mode) are first moved by
+ * the field (bilinear between the grid's pixel centres, constant beyond
+ * the outermost ones, clamped to the unit square).  The moved map is
+ * rasterised and its max area error computed; if it folded (a pixel
+ * centre claimed by two regions) or its error is not below that of the
+ * plain start, the plain start is used instead and CG_FLAG_FALLBACK is
+ * set for that step.  The plain iteration then runs as usual.
  * Blocking: starts after the work already queued on `stream` and
  * returns when all steps have stopped.  Iterations are issued
  * as captured HIP graphs of `graph_iters` iterations (0: default 8; a

@@ -174,6 +174,14 @@ def density_texture(labels, lut):
     return lut[labels.astype(np.int64)]
 
 
+def log_density(labels, counts, values, b: float = 1.0):
+    """Input of the learned warm start: log of the Step-3 density over its
+    mean over the texture."""
+    lut, _ = density_lut(counts, values, b)
+    d = density_texture(labels, lut)
+    return np.log(d / d.mean())
+
+
 # ----------------------------------------------------------------------------
 # Step 4: integral images (reading R1, R2; eq.(1))
 
@@ -285,6 +293,37 @@ def displacement(im: InIm):
     tx, ty = eight_anchor_map(im)
     ux, uy = t_uniform(N)
     return tx - ux, ty - uy
+
+
+# ----------------------------------------------------------------------------
+# Warm start (not in the paper): a displacement field at the pixel centres
+# of a G x G grid moves the starting positions before the iteration.
+
+
+def warm_start_move(xy: np.ndarray, field: np.ndarray) -> np.ndarray:
+    """Bilinear interpolation of field[j][i] = (dx, dy) given at
+    ((i + 1/2)/G, (j + 1/2)/G), constant beyond the outermost centres,
+    then clamp to the unit square."""
+    G = field.shape[0]
+    if G == 1:
+        d = np.broadcast_to(field[0, 0], xy.shape)
+    else:
+        u = np.clip(xy[:, 0] * G - 0.5, 0.0, G - 1.0)
+        v = np.clip(xy[:, 1] * G - 0.5, 0.0, G - 1.0)
+        i0 = np.minimum(np.floor(u).astype(np.int64), G - 2)
+        j0 = np.minimum(np.floor(v).astype(np.int64), G - 2)
+        fx = (u - i0)[:, None]
+        fy = (v - j0)[:, None]
+        d = ((1 - fx) * (1 - fy) * field[j0, i0] + fx * (1 - fy) * field[j0, i0 + 1]
+             + (1 - fx) * fy * field[j0 + 1, i0] + fx * fy * field[j0 + 1, i0 + 1])
+    return np.clip(xy + d, 0.0, 1.0)
+
+
+def tracer_grid(G: int) -> np.ndarray:
+    """Pixel centres ((i + 1/2)/G, (j + 1/2)/G), row-major over j, [G*G][2]."""
+    c = (np.arange(G) + 0.5) / G
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
 
 
 # ----------------------------------------------------------------------------

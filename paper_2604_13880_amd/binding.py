@@ -40,6 +40,11 @@ class CgSeriesDesc(C.Structure):
                 ("init_field", C.c_void_p), ("init_G", C.c_int32)]
 
 
+class CgNetConfig(C.Structure):
+    _fields_ = [("base_channels", C.c_int32), ("levels", C.c_int32), ("height", C.c_int32),
+                ("width", C.c_int32), ("max_batch", C.c_int32), ("out_scale", C.c_float), ("seed", C.c_uint64)]
+
+
 class CgSeriesOut(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("extra_xy", C.c_void_p), ("frames", C.c_void_p),
                 ("iters", C.c_void_p), ("status", C.c_void_p), ("flags", C.c_void_p),
@@ -76,6 +81,20 @@ def lib():
             "cg_set_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, i32, i32]),
             "cg_profile_stage": (C.c_int, [vp, C.c_char_p, i32]),
             "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
+            "cg_log_density": (C.c_int, [vp, C.c_int, vp, vp, vp, i32, C.c_float, vp, vp]),
+            "cg_tracer_field": (C.c_int, [vp, i32, vp, vp, vp]),
+            "cg_net_create": (C.c_int, [vp, C.POINTER(CgNetConfig), C.POINTER(vp)]),
+            "cg_net_destroy": (C.c_int, [vp]),
+            "cg_net_n_params": (i64, [vp]),
+            "cg_net_get_params": (C.c_int, [vp, vp, vp]),
+            "cg_net_set_params": (C.c_int, [vp, vp, vp]),
+            "cg_net_get_grads": (C.c_int, [vp, vp, vp]),
+            "cg_net_zero_grads": (C.c_int, [vp, vp]),
+            "cg_net_forward": (C.c_int, [vp, vp, i32, vp, vp]),
+            "cg_net_backward": (C.c_int, [vp, vp, i32, vp, vp]),
+            "cg_net_adam_step": (C.c_int, [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
+            "cg_net_save": (C.c_int, [vp, C.c_char_p]),
+            "cg_net_load": (C.c_int, [vp, C.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -89,7 +108,9 @@ def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
             "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
             "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
-            "cg_profile_read"]
+            "cg_profile_read", "cg_log_density", "cg_tracer_field", "cg_net_create", "cg_net_destroy",
+            "cg_net_n_params", "cg_net_get_params", "cg_net_set_params", "cg_net_get_grads", "cg_net_zero_grads",
+            "cg_net_forward", "cg_net_backward", "cg_net_adam_step", "cg_net_save", "cg_net_load"]
 
 
 def _ptr(t):
@@ -253,6 +274,29 @@ class Context:
         self._check(rc, "cg_region_areas")
         return areas, ex
 
+    def log_density(self, labels, counts, values, shape: float = 1.0):
+        """log(d / mean d) of the Step-3 density from a label map and pixel counts."""
+        N = int(labels.shape[-1])
+        vals = _dev(values, torch.float32)
+        out = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        rc = lib().cg_log_density(self.handle, N, _ptr(labels.contiguous()), _ptr(counts), _ptr(vals),
+                                  int(vals.numel()), float(shape), _ptr(out), _stream())
+        self._check(rc, "cg_log_density")
+        return out
+
+    def tracer_grid(self, G: int):
+        """Pixel-centre positions of a G x G grid, float32 [G*G, 2]."""
+        out = torch.empty((G * G, 2), dtype=torch.float32, device="cuda")
+        self._check(lib().cg_tracer_field(self.handle, int(G), None, _ptr(out), _stream()), "cg_tracer_field")
+        return out
+
+    def tracer_field(self, G: int, final_xy):
+        """Displacement of moved tracers from their pixel centres, float32 [G, G, 2]."""
+        fin = _dev(final_xy, torch.float32, (-1, 2))
+        out = torch.empty((G, G, 2), dtype=torch.float32, device="cuda")
+        self._check(lib().cg_tracer_field(self.handle, int(G), _ptr(fin), _ptr(out), _stream()), "cg_tracer_field")
+        return out
+
     def profile_stage(self, stage: str | None, every: int = 1):
         self._check(lib().cg_profile_stage(self.handle, (stage or "").encode(), int(every)), "cg_profile_stage")
 
@@ -280,7 +324,8 @@ class Context:
         """Run cartogram series.  Each dict: map (Map), xy0 (float32 [n,2]),
         N, values ([T,R] or [R]), and optional mode, shape, area_source,
         tol, patience, max_iters, fixed_iters, precision, frames, extra
-        ([m,2] tracer points), init_field ([2,G+1,G+1]).  Returns one dict
+        ([m,2] tracer points), init_field ([G,G,2] warm-start displacement at
+        pixel centres).  Returns one dict
         per series with xy [T,n,2], extra_xy, frames, iters, status,
         flags, eps, xi (host numpy for the scalars)."""
         descs = (CgSeriesDesc * len(series))()
@@ -322,7 +367,7 @@ class Context:
             d.extra = 0 if extra is None else extra.data_ptr()
             d.n_extra = 0 if extra is None else int(extra.shape[0])
             d.init_field = 0 if field is None else field.data_ptr()
-            d.init_G = 0 if field is None else int(field.shape[-1]) - 1
+            d.init_G = 0 if field is None else int(field.shape[0])
             o = outs[k]
             o.xy = xy.data_ptr()
             o.extra_xy = 0 if exy is None else exy.data_ptr()
@@ -334,3 +379,73 @@ class Context:
         rc = lib().cg_step_series(self.handle, descs, len(series), outs, int(graph_iters), _stream())
         self._check(rc, "cg_step_series")
         return results
+
+
+class Net:
+    """Learned warm start (include/cg_net.h): U-Net trained and run by the
+    library's own kernels."""
+
+    def __init__(self, ctx: Context, base_channels: int = 32, levels: int = 4, height: int = 512,
+                 width: int = 512, max_batch: int = 8, out_scale: float = 0.1, seed: int = 0):
+        self.ctx = ctx
+        cfg = CgNetConfig(int(base_channels), int(levels), int(height), int(width), int(max_batch),
+                          float(out_scale), int(seed))
+        h = C.c_void_p()
+        ctx._check(lib().cg_net_create(ctx.handle, C.byref(cfg), C.byref(h)), "cg_net_create")
+        self.handle = h
+        self.H, self.W, self.max_batch = int(height), int(width), int(max_batch)
+        self.n_params = int(lib().cg_net_n_params(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cg_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self.ctx._check(lib().cg_net_get_params(self.handle, _ptr(out), _stream()), "cg_net_get_params")
+        return out
+
+    def set_params(self, p):
+        p = _dev(p, torch.float32)
+        if p.numel() != self.n_params:
+            raise CartogramError(f"expected {self.n_params} parameters, got {p.numel()}")
+        self.ctx._check(lib().cg_net_set_params(self.handle, _ptr(p), _stream()), "cg_net_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def grads(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self.ctx._check(lib().cg_net_get_grads(self.handle, _ptr(out), _stream()), "cg_net_get_grads")
+        return out
+
+    def zero_grads(self):
+        self.ctx._check(lib().cg_net_zero_grads(self.handle, _stream()), "cg_net_zero_grads")
+
+    def forward(self, x, out=None) -> torch.Tensor:
+        x = _dev(x, torch.float32)
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty((B, self.H, self.W, 2), dtype=torch.float32, device="cuda")
+        self.ctx._check(lib().cg_net_forward(self.handle, _ptr(x), B, _ptr(out), _stream()), "cg_net_forward")
+        return out
+
+    def backward(self, target, loss=None):
+        t = _dev(target, torch.float32)
+        B = int(t.shape[0])
+        self.ctx._check(lib().cg_net_backward(self.handle, _ptr(t), B, _ptr(loss), _stream()), "cg_net_backward")
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.ctx._check(lib().cg_net_adam_step(self.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                               _stream()), "cg_net_adam_step")
+
+    def save(self, path: str):
+        self.ctx._check(lib().cg_net_save(self.handle, path.encode()), "cg_net_save")
+
+    def load(self, path: str):
+        self.ctx._check(lib().cg_net_load(self.handle, path.encode()), "cg_net_load")

@@ -21,6 +21,8 @@
 
 #include "cg.h"
 #include "cg_dev.h"
+#include "cg_net.h"
+#include "host.h"
 
 namespace cgk {
 void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
@@ -31,6 +33,10 @@ bool sat_shape_supported(int tw, int th);
 void launch_density(const Batch& B, hipStream_t s);
 void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s);
 void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s);
+void launch_restore(const Batch& B, int64_t pt_blocks, hipStream_t s);
+void launch_log_density(const uint16_t* labels, const int64_t* counts, const float* values, int R, int N, float shape,
+                        float* lut, float* out, hipStream_t s);
+void launch_tracer_field(int G, const float* fin, float* out, hipStream_t s);
 void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s);
 void launch_err(const Batch& B, int mode, hipStream_t s);
 void launch_init(const Batch& B, int64_t pt_blocks, hipStream_t s);
@@ -43,96 +49,10 @@ using cgk::Inst;
 using cgk::IterState;
 using cgk::SatLayout;
 
-namespace {
-
-struct DevBuf {
-  char* p = nullptr;
-  size_t n = 0;
-};
-
+using namespace cgh;
 using cgk::kFillRows;
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-}  // namespace
-
-struct cg_map {
-  cg_ctx* ctx = nullptr;
-  int32_t n_vert = 0, R = 0, n_rings = 0, n_edges = 0;
-  int4* d_edges = nullptr;
-  int32_t* d_ring_off = nullptr;
-  int32_t* d_ring_idx = nullptr;
-  int32_t* d_reg_ring_off = nullptr;
-  int32_t* d_reg_rings = nullptr;
-};
-
-struct cg_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;  // private stream of the series driver (graph capture)
-  hipStream_t last = nullptr;
-  bool last_set = false;
-  std::string err;
-  std::map<std::string, DevBuf> bufs;
-  char* pinned = nullptr;
-  size_t pinned_n = 0;
-  hipEvent_t pinned_ev = nullptr;
-  bool pinned_pending = false;
-  std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tiles;  // (N, prec, batch px) -> shape
-  // per-stage timing of series iterations
-  int prof_stage = -1;
-  int prof_every = 1;        // time one launch in every prof_every iterations
-  std::vector<hipEvent_t> prof_ev;
-  int prof_k = 0;            // iterations recorded per graph replay
-  double prof_ms = 0.0;
-  int64_t prof_launches = 0;
-  int64_t prof_failed = 0;
-  hipStream_t prof_stream = nullptr;
-};
 
 namespace {
-
-int fail(cg_ctx* c, int code, const std::string& msg) {
-  if (c) c->err = msg;
-  return code;
-}
-
-#define HIP_OK(ctx, expr)                                                               \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(ctx, CG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-// The stream a call runs on: the caller's (NULL is the HIP null stream).
-// Scratch buffers are shared between calls, so switching streams first
-// drains the previous one.
-hipStream_t pick_stream(cg_ctx* c, void* s) {
-  hipStream_t st = (hipStream_t)s;
-  if (c->last_set && c->last != st) hipStreamSynchronize(c->last);
-  c->last = st;
-  c->last_set = true;
-  return st;
-}
-
-// Grow-only named device buffers (stream-ordered reuse).
-int get_buf(cg_ctx* c, const char* name, size_t bytes, hipStream_t st, char** out) {
-  DevBuf& b = c->bufs[name];
-  if (b.n < bytes) {
-    if (b.p) {
-      HIP_OK(c, hipStreamSynchronize(st));
-      HIP_OK(c, hipFree(b.p));
-      b.p = nullptr;
-      b.n = 0;
-    }
-    size_t want = std::max(bytes, (size_t)4096);
-    want = want + want / 4;
-    HIP_OK(c, hipMalloc(&b.p, want));
-    b.n = want;
-  }
-  *out = b.p;
-  return CG_OK;
-}
 
 // Host -> device copy through a pinned staging buffer guarded by an event.
 int upload(cg_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t st) {
@@ -153,8 +73,6 @@ int upload(cg_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t st) 
   c->pinned_pending = true;
   return CG_OK;
 }
-
-bool pow2_ok(int N) { return N >= 16 && N <= 8192 && (N & (N - 1)) == 0; }
 
 size_t store_size(int prec) { return prec == CG_F64 ? 8 : 4; }
 size_t carry_size(int prec) { return prec == CG_F32 ? 4 : 8; }  // COMP, F64, F64ACC carry in double
@@ -832,6 +750,31 @@ int cg_profile_read(cg_ctx* c, double* total_ms, int64_t* launches) {
   return CG_OK;
 }
 
+int cg_log_density(cg_ctx* c, int N, const uint16_t* labels, const int64_t* counts, const float* values,
+                   int32_t n_regions, float shape, float* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!labels || !counts || !values || !out) return fail(c, CG_EINVAL, "cg_log_density: null argument");
+  if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_log_density: N must be a power of two in [16, 8192]");
+  if (n_regions < 1 || n_regions > 65535 || !(shape >= 0))
+    return fail(c, CG_EINVAL, "cg_log_density: need 1 <= n_regions <= 65535 and shape >= 0");
+  (void)hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  char* lut = nullptr;
+  int rc = get_buf(c, "log_lut", sizeof(float) * (size_t)(n_regions + 1), st, &lut);
+  if (rc) return rc;
+  cgk::launch_log_density(labels, counts, values, n_regions, N, shape, (float*)lut, out, st);
+  return check_launch(c);
+}
+
+int cg_tracer_field(cg_ctx* c, int32_t G, const float* final_xy, float* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!out || G < 1 || G > 65536) return fail(c, CG_EINVAL, "cg_tracer_field: need out and 1 <= G <= 65536");
+  (void)hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  cgk::launch_tracer_field(G, final_xy, out, st);
+  return check_launch(c);
+}
+
 int cg_tile_shape(const cg_ctx* c, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th) {
   if (!c || !tw || !th || !pow2_ok(N)) return CG_EINVAL;
   int a, b;
@@ -870,7 +813,19 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
   if (rc) return rc;
   const int n = P.n;
   cgk::launch_init(P.B, P.pt_blocks, st);
-  cgk::launch_apply_field(P.B, P.pt_blocks, st);
+  bool warm = false;
+  for (auto& s : specs) warm = warm || s.init_field != nullptr;
+  if (warm) {
+    // warm start: error of the plain start, move by the field, rasterise the
+    // moved map (fold check), judge it, restore the rejected ones
+    cgk::launch_areas(P.B, P.reg_blocks, st);
+    cgk::launch_err(P.B, 2, st);
+    cgk::launch_apply_field(P.B, P.pt_blocks, st);
+    cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+    cgk::launch_areas(P.B, P.reg_blocks, st);
+    cgk::launch_err(P.B, 3, st);
+    cgk::launch_restore(P.B, P.pt_blocks, st);
+  }
   cgk::launch_areas(P.B, P.reg_blocks, st);
   cgk::launch_err(P.B, 0, st);
   if ((rc = check_launch(c))) return rc;

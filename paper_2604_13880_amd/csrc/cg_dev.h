@@ -41,6 +41,7 @@ struct IterState {
   int64_t xings;      // row crossings in the latest label map
   double xi, eps, best_xi;
   double d0, C;       // density parameters of the latest iteration
+  double xi0;         // max error of the plain (not warm-started) start
 };
 
 struct Inst {

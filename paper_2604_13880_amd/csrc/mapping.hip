@@ -162,8 +162,10 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   *ptr = o;
 }
 
-// Warm start: move every point by a given displacement field sampled at
-// the nodes of a G x G grid ([2][G+1][G+1]), bilinearly, then clamp.
+// Warm start: move every point by a displacement field given at the pixel
+// centres of a G x G grid ([G][G][2], centre (i + 1/2, j + 1/2) / G),
+// interpolated bilinearly (constant beyond the outermost centres), then
+// clamp to the unit square.
 __global__ __launch_bounds__(256) void k_apply_field(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
@@ -173,16 +175,85 @@ __global__ __launch_bounds__(256) void k_apply_field(Batch B) {
   float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
   const float2 p = *ptr;
   const int G = (int)I.init_G;
-  const float u = fminf(fmaxf(p.x * G, 0.f), (float)G), v = fminf(fmaxf(p.y * G, 0.f), (float)G);
-  const int i0 = min((int)floorf(u), G - 1), j0 = min((int)floorf(v), G - 1);
-  const float fx = u - i0, fy = v - j0;
-  const int64_t P = (int64_t)(G + 1) * (G + 1);
-  const float* F0 = I.init_field;
-  auto at = [&](int c, int i, int j) { return F0[c * P + (int64_t)j * (G + 1) + i]; };
-  const float w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
-  const float dx = w00 * at(0, i0, j0) + w10 * at(0, i0 + 1, j0) + w01 * at(0, i0, j0 + 1) + w11 * at(0, i0 + 1, j0 + 1);
-  const float dy = w00 * at(1, i0, j0) + w10 * at(1, i0 + 1, j0) + w01 * at(1, i0, j0 + 1) + w11 * at(1, i0 + 1, j0 + 1);
+  const float2* F = (const float2*)I.init_field;
+  float dx, dy;
+  if (G == 1) {
+    dx = F[0].x;
+    dy = F[0].y;
+  } else {
+    const float u = fminf(fmaxf(p.x * G - 0.5f, 0.f), (float)(G - 1));
+    const float v = fminf(fmaxf(p.y * G - 0.5f, 0.f), (float)(G - 1));
+    const int i0 = min((int)floorf(u), G - 2), j0 = min((int)floorf(v), G - 2);
+    const float fx = u - i0, fy = v - j0;
+    const float2 a = F[(int64_t)j0 * G + i0], b = F[(int64_t)j0 * G + i0 + 1];
+    const float2 c = F[(int64_t)(j0 + 1) * G + i0], d = F[(int64_t)(j0 + 1) * G + i0 + 1];
+    const float w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+    dx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+    dy = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+  }
   *ptr = make_float2(fminf(fmaxf(p.x + dx, 0.f), 1.f), fminf(fmaxf(p.y + dy, 0.f), 1.f));
+}
+
+// Warm start rejected: put the starting positions back.
+__global__ __launch_bounds__(256) void k_restore(Batch B) {
+  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  if (I.init_field == nullptr || !(I.st->flags & CG_FLAG_FALLBACK)) return;
+  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  if (idx >= I.n_pts) return;
+  if (idx < I.n_vert) {
+    if (I.src_xy && I.src_xy != I.xy) I.xy[idx] = I.src_xy[idx];
+  } else {
+    const int64_t e = idx - I.n_vert;
+    if (I.src_extra && I.src_extra != I.extra) I.extra[e] = I.src_extra[e];
+  }
+}
+
+// Per-region log-density table of Step 3 from the pixel counts: lut[v] =
+// log(d(v) / mean d), d(v) = s(v)/o(v), d(0) = shape * d0 (one block).
+__global__ __launch_bounds__(256) void k_log_lut(const int64_t* counts, const float* values, int R, int N, float shape,
+                                                 float* lut) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double ss = 0.0, so = 0.0;
+  for (int v = 1 + t; v <= R; v += 256) {
+    const int64_t o = counts[v];
+    if (o > 0) {
+      ss += (double)values[v - 1];
+      so += (double)o;
+    }
+  }
+  ss = block_sum(ss, red);
+  so = block_sum(so, red);
+  const double d0 = so > 0.0 ? ss / so : 1.0;
+  const double bdv = (double)shape * d0;
+  const double C = ss + bdv * (double)counts[0];
+  const double mean = C / ((double)N * (double)N);
+  const double tiny = 1e-30;
+  for (int v = t; v <= R; v += 256) {
+    double d;
+    if (v == 0) d = bdv;
+    else d = counts[v] > 0 ? (double)values[v - 1] / (double)counts[v] : 0.0;
+    lut[v] = (float)log(fmax(d, tiny) / fmax(mean, tiny));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_log_density(const uint16_t* labels, const float* lut, int R, int64_t n,
+                                                     float* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int v = labels[i];
+  out[i] = v <= R ? lut[v] : lut[0];
+}
+
+// Pixel-centre tracer grid, or the displacement of moved tracers from it.
+__global__ __launch_bounds__(256) void k_tracer_field(int G, const float2* fin, float2* out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)G * G) return;
+  const int j = (int)(idx / G), i = (int)(idx - (int64_t)j * G);
+  const float cx = ((float)i + 0.5f) / (float)G, cy = ((float)j + 0.5f) / (float)G;
+  if (fin) out[idx] = make_float2(fin[idx].x - cx, fin[idx].y - cy);
+  else out[idx] = make_float2(cx, cy);
 }
 
 // Shoelace area of every region (sum over its rings), FP64, fixed order.
@@ -209,7 +280,10 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
 
 // Cartographic errors and the stopping rule (Method, end of the static
 // construction).  mode 0: update the iteration state; mode 1: evaluate
-// only (eps, xi into the state, nothing else touched).
+// only (eps, xi into the state, nothing else touched); mode 2: also keep
+// xi as the error of the plain start; mode 3: judge a warm start (instances
+// with a field): rejected, with CG_FLAG_FALLBACK, if the moved map folded
+// (contested pixels) or its error is not below the plain start's.
 __global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
@@ -240,7 +314,9 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
   I.areas[0] = 1.0 - sa;
   st->xi = xi;
   st->eps = eps;
-  if (mode == 1) return;
+  if (mode == 2) st->xi0 = xi;
+  if (mode == 3 && I.init_field != nullptr && (st->contested > 0 || !(xi < st->xi0))) st->flags |= CG_FLAG_FALLBACK;
+  if (mode != 0) return;
   int it;
   if (!st->evaluated) {
     st->evaluated = 1;
@@ -324,6 +400,20 @@ void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s) {
 }
 void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s) {
   if (pt_blocks > 0) hipLaunchKernelGGL(k_apply_field, dim3(pt_blocks), dim3(256), 0, s, B);
+}
+void launch_restore(const Batch& B, int64_t pt_blocks, hipStream_t s) {
+  if (pt_blocks > 0) hipLaunchKernelGGL(k_restore, dim3(pt_blocks), dim3(256), 0, s, B);
+}
+void launch_log_density(const uint16_t* labels, const int64_t* counts, const float* values, int R, int N, float shape,
+                        float* lut, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_lut, dim3(1), dim3(256), 0, s, counts, values, R, N, shape, lut);
+  const int64_t n = (int64_t)N * N;
+  hipLaunchKernelGGL(k_log_density, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, labels, lut, R, n, out);
+}
+void launch_tracer_field(int G, const float* fin, float* out, hipStream_t s) {
+  const int64_t n = (int64_t)G * G;
+  hipLaunchKernelGGL(k_tracer_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, (const float2*)fin,
+                     (float2*)out);
 }
 void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s) {
   if (region_blocks > 0) hipLaunchKernelGGL(k_areas, dim3(region_blocks), dim3(256), 0, s, B);

@@ -1,0 +1,613 @@
+// Kernels of the learned warm start: a convolutional encoder-decoder
+// (U-Net) that maps a log-density texture to the displacement field of the
+// converged cartogram.  The net is not part of the paper; it follows the
+// paper's remark that a good starting deformation (the previous step of a
+// series) shortens the iteration, and is always checked by the plain
+// iteration that follows it.
+//
+// Activations are bfloat16 in NHWC order ([batch][row][column][channel]);
+// every convolution accumulates in float32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16).  A 3x3 convolution with C_in input channels
+// is an implicit GEMM with K = 9 C_in, k = tap * C_in + c (tap = 3 ky + kx):
+//   forward      out[p][o]  = sum_k W[o][k] * patch(in)[p][k]
+//   input grad   gin[p][c]  = sum_k W'[c][k'] * patch(g)[p][k']
+//                (W'[c][tap' C_out + o] = W[o][(8 - tap') C_in + c])
+//   weight grad  dW[o][k]   = sum_p g[p][o] * patch(in)[p][k]
+// The first two share one kernel (weights as the A operand, 16 output
+// channels per fragment row, 16 pixels per fragment column); the third
+// stages pixel-major tiles in LDS transposed so that the pixel index
+// becomes the MFMA reduction axis.
+#include "cg_net_dev.h"
+
+namespace cgn {
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *(const u32x4*)p);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u}); }
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution (stride 1, zero padding 1) as an implicit GEMM.
+// Block: 4 wavefronts x 64 pixels = 256 pixels, 16*MF output channels.
+// GEN = element-wise operand gathers (any C_in; used for C_in % 32 != 0).
+template <int MF, bool GEN>
+__global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, int Cin,
+                                               const uint16_t* __restrict__ wA, const float* __restrict__ bias,
+                                               uint16_t* __restrict__ out, int Cout, int64_t P, int H, int W,
+                                               int relu) {
+  constexpr int NF = 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kq = lane >> 4, lr = lane & 15;
+  const int64_t px0 = (int64_t)blockIdx.x * 256 + wv * 64;
+  const int co0 = blockIdx.y * (16 * MF);
+  const int K = 9 * Cin;
+  const int64_t HW = (int64_t)H * W;
+  int64_t pimg[NF];
+  int py[NF], pxx[NF];
+  bool pv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int64_t p = px0 + 16 * f + lr;
+    pv[f] = p < P;
+    const int64_t b = pv[f] ? p / HW : 0;
+    const int64_t rem = pv[f] ? p - b * HW : 0;
+    py[f] = (int)(rem / W);
+    pxx[f] = (int)(rem - (int64_t)py[f] * W);
+    pimg[f] = b * HW;
+  }
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int m = 0; m < MF; ++m)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (!GEN) {
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const uint16_t* src[NF];
+      bool ok[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int yy = py[f] + dy, xx = pxx[f] + dx;
+        ok[f] = pv[f] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        src[f] = in + (ok[f] ? ((pimg[f] + (int64_t)yy * W + xx) * Cin + 8 * kq) : 0);
+      }
+      const uint16_t* wrow = wA + (int64_t)(co0 + lr) * K + tap * Cin + 8 * kq;
+      for (int c0 = 0; c0 < Cin; c0 += 32) {
+        bf16x8 a[MF], bb[NF];
+#pragma unroll
+        for (int m = 0; m < MF; ++m) a[m] = load8(wrow + (int64_t)16 * m * K + c0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) bb[f] = ok[f] ? load8(src[f] + c0) : zero8();
+#pragma unroll
+        for (int m = 0; m < MF; ++m)
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+            acc[m][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[f], acc[m][f], 0, 0, 0);
+      }
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8 a[MF], bb[NF];
+#pragma unroll
+      for (int m = 0; m < MF; ++m) {
+        const uint16_t* wr = wA + (int64_t)(co0 + 16 * m + lr) * K;
+        u16x8 tv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + 8 * kq + e;
+          tv[e] = k < K ? wr[k] : (uint16_t)0;
+        }
+        a[m] = __builtin_bit_cast(bf16x8, tv);
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        u16x8 tv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + 8 * kq + e;
+          uint16_t v = 0;
+          if (k < K && pv[f]) {
+            const int tap = k / Cin, c = k - tap * Cin;
+            const int yy = py[f] + tap / 3 - 1, xx = pxx[f] + tap % 3 - 1;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = in[(pimg[f] + (int64_t)yy * W + xx) * Cin + c];
+          }
+          tv[e] = v;
+        }
+        bb[f] = __builtin_bit_cast(bf16x8, tv);
+      }
+#pragma unroll
+      for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          acc[m][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[f], acc[m][f], 0, 0, 0);
+    }
+  }
+  // lane holds D[o = 4 kq + r][pixel = lr] of every fragment
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int64_t p = px0 + 16 * f + lr;
+    if (p >= P) continue;
+#pragma unroll
+    for (int m = 0; m < MF; ++m) {
+      const int o = co0 + 16 * m + 4 * kq;
+      u16x4 tv;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[m][f][r] + (bias ? bias[o + r] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        tv[r] = f2bf(v);
+      }
+      *(u16x4*)(out + p * Cout + o) = tv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient dW[o][k] += sum_p g[p][o] * patch(in)[p][k].
+// Block: 32 output channels x 128 columns of K, 4 wavefronts each owning 32
+// columns; pixels in steps of 32 staged in LDS transposed ([channel][pixel]);
+// partial sums are added to the float32 gradient with atomics.
+constexpr int kWgPix = 32;
+constexpr int kWgPad = kWgPix + 8;   // row pitch in LDS (elements)
+
+template <bool GEN>
+__global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict__ in, int Cin,
+                                                     const uint16_t* __restrict__ g, int Cout,
+                                                     float* __restrict__ dW, int64_t P, int H, int W,
+                                                     int64_t px_per_block) {
+  __shared__ __align__(16) uint16_t As[32][kWgPad];    // g tile [o][pixel]
+  __shared__ __align__(16) uint16_t Bs[128][kWgPad];   // patch tile [k][pixel]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int kq = lane >> 4, lr = lane & 15;
+  const int K = 9 * Cin;
+  const int k0 = blockIdx.x * 128;
+  const int o0 = blockIdx.y * 32;
+  const int64_t pbeg = (int64_t)blockIdx.z * px_per_block;
+  const int64_t pend = pbeg + px_per_block < P ? pbeg + px_per_block : P;
+  const int64_t HW = (int64_t)H * W;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int f = 0; f < 2; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kWgPix) {
+    __syncthreads();
+    // g tile: 32 pixels x 32 channels = 128 chunks of 8 channels
+    if (t < 128) {
+      const int pi = t >> 2, cc = (t & 3) * 8;
+      const int64_t p = p0 + pi;
+      u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (p < pend) v = *(const u16x8*)(g + p * Cout + o0 + cc);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[cc + e][pi] = v[e];
+    }
+    // patch tile: 32 pixels x 128 columns of K
+    if (!GEN) {
+      for (int c = t; c < kWgPix * 16; c += 256) {
+        const int pi = c >> 4, kk = (c & 15) * 8;
+        const int64_t p = p0 + pi;
+        const int k = k0 + kk;
+        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        bool ok = p < pend && k < K;
+        int64_t at = 0;
+        if (ok) {
+          const int tap = k / Cin, ci = k - tap * Cin;
+          const int64_t b = p / HW, rem = p - b * HW;
+          const int y = (int)(rem / W), x = (int)(rem - (int64_t)y * W);
+          const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+          ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+          at = (b * HW + (int64_t)yy * W + xx) * Cin + ci;
+        }
+        if (ok) v = *(const u16x8*)(in + at);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[kk + e][pi] = v[e];
+      }
+    } else {
+      for (int c = t; c < kWgPix * 128; c += 256) {
+        const int pi = c >> 7, kk = c & 127;
+        const int64_t p = p0 + pi;
+        const int k = k0 + kk;
+        uint16_t v = 0;
+        if (p < pend && k < K) {
+          const int tap = k / Cin, ci = k - tap * Cin;
+          const int64_t b = p / HW, rem = p - b * HW;
+          const int y = (int)(rem / W), x = (int)(rem - (int64_t)y * W);
+          const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+          if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = in[(b * HW + (int64_t)yy * W + xx) * Cin + ci];
+        }
+        Bs[kk][pi] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kWgPix; kk += 32) {
+      bf16x8 a[2], bb[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) a[m] = load8(&As[16 * m + lr][kk + 8 * kq]);
+#pragma unroll
+      for (int f = 0; f < 2; ++f) bb[f] = load8(&Bs[32 * wv + 16 * f + lr][kk + 8 * kq]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+          acc[m][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[f], acc[m][f], 0, 0, 0);
+    }
+  }
+  // lane holds D[o = 4 kq + r][k = lr] of every fragment
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int k = k0 + 32 * wv + 16 * f + lr;
+      if (k >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + 16 * m + 4 * kq + r;
+        atomicAdd(dW + (int64_t)o * K + k, acc[m][f][r]);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise and reshaping kernels (8 channels per thread)
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// g <- g where act > 0, else 0 (ReLU backward; act is the stored output)
+__global__ __launch_bounds__(256) void k_relu_mask(uint16_t* __restrict__ g, const uint16_t* __restrict__ act, int64_t n8) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n8) return;
+  u16x8 gv = *(const u16x8*)(g + 8 * i);
+  const u16x8 av = *(const u16x8*)(act + 8 * i);
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (!(bf2f(av[e]) > 0.f)) gv[e] = 0;
+  *(u16x8*)(g + 8 * i) = gv;
+}
+
+// 2x2 average pooling, [B][H][W][C] -> [B][H/2][W/2][C]
+__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int Bn, int H,
+                                              int W, int C) {
+  const int C8 = C / 8, Ho = H / 2, Wo = W / 2;
+  const int64_t n = (int64_t)Bn * Ho * Wo * C8;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c8 = (int)(i % C8);
+  int64_t r = i / C8;
+  const int xo = (int)(r % Wo);
+  r /= Wo;
+  const int yo = (int)(r % Ho);
+  const int64_t b = r / Ho;
+  const uint16_t* s = x + (((b * H + 2 * yo) * W + 2 * xo) * C + 8 * c8);
+  const u16x8 a0 = *(const u16x8*)s, a1 = *(const u16x8*)(s + C), a2 = *(const u16x8*)(s + (int64_t)W * C),
+              a3 = *(const u16x8*)(s + (int64_t)W * C + C);
+  u16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = f2bf(0.25f * (bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e])));
+  *(u16x8*)(y + i * 8) = o;
+}
+
+// cat[b][y][x] = (deep[b][y/2][x/2][0:Cd], skip[b][y][x][0:Cs])
+__global__ __launch_bounds__(256) void k_upcat(const uint16_t* __restrict__ deep, int Cd, const uint16_t* __restrict__ skip,
+                                               int Cs, uint16_t* __restrict__ cat, int Bn, int H, int W) {
+  const int C8 = (Cd + Cs) / 8;
+  const int64_t n = (int64_t)Bn * H * W * C8;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % C8) * 8;
+  const int64_t p = i / C8;
+  const int x = (int)(p % W);
+  const int64_t r = p / W;
+  const int y = (int)(r % H);
+  const int64_t b = r / H;
+  u16x8 v;
+  if (c < Cd) v = *(const u16x8*)(deep + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cd + c);
+  else v = *(const u16x8*)(skip + p * Cs + (c - Cd));
+  *(u16x8*)(cat + p * (Cd + Cs) + c) = v;
+}
+
+// gdeep[b][y][x][c] = sum over the 2x2 children of gcat[..][c], c < Cd
+__global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ gcat, int Ccat, int Cd,
+                                                 uint16_t* __restrict__ gdeep, int Bn, int Ho, int Wo) {
+  const int C8 = Cd / 8;
+  const int64_t n = (int64_t)Bn * Ho * Wo * C8;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % C8) * 8;
+  int64_t r = i / C8;
+  const int xo = (int)(r % Wo);
+  r /= Wo;
+  const int yo = (int)(r % Ho);
+  const int64_t b = r / Ho;
+  const int W = 2 * Wo, H = 2 * Ho;
+  const int64_t p = (b * H + 2 * yo) * W + 2 * xo;
+  const uint16_t* s = gcat + p * Ccat + c;
+  const u16x8 a0 = *(const u16x8*)s, a1 = *(const u16x8*)(s + Ccat), a2 = *(const u16x8*)(s + (int64_t)W * Ccat),
+              a3 = *(const u16x8*)(s + (int64_t)W * Ccat + Ccat);
+  u16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = f2bf(bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e]));
+  *(u16x8*)(gdeep + i * 8) = o;
+}
+
+// gskip[b][y][x][c] = gcat[b][y][x][Cd + c] (if gcat) + gpool[b][y/2][x/2][c] / 4 (if gpool)
+__global__ __launch_bounds__(256) void k_skip_grad(const uint16_t* __restrict__ gcat, int Ccat, int Cd,
+                                                   const uint16_t* __restrict__ gpool, uint16_t* __restrict__ gskip,
+                                                   int Cs, int Bn, int H, int W) {
+  const int C8 = Cs / 8;
+  const int64_t n = (int64_t)Bn * H * W * C8;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % C8) * 8;
+  const int64_t p = i / C8;
+  const int x = (int)(p % W);
+  const int64_t r = p / W;
+  const int y = (int)(r % H);
+  const int64_t b = r / H;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = 0.f;
+  if (gcat) {
+    const u16x8 a = *(const u16x8*)(gcat + p * Ccat + Cd + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] += bf2f(a[e]);
+  }
+  if (gpool) {
+    const u16x8 a = *(const u16x8*)(gpool + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cs + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] += 0.25f * bf2f(a[e]);
+  }
+  u16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = f2bf(v[e]);
+  *(u16x8*)(gskip + p * Cs + c) = o;
+}
+
+// bias gradient: db[c] += sum_p g[p][c]; block = 256 pixels-chunks x C channels
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ g, int C, int64_t P,
+                                                   int64_t px_per_block, float* __restrict__ db) {
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int lanes_per_px = C < 256 ? C : 256;   // C is 32, 64, 128 or a multiple of 256
+  const int rows = 256 / lanes_per_px;
+  const int64_t pbeg = (int64_t)blockIdx.x * px_per_block;
+  const int64_t pend = pbeg + px_per_block < P ? pbeg + px_per_block : P;
+  for (int cbase = 0; cbase < C; cbase += lanes_per_px) {
+    const int c = cbase + t % lanes_per_px, row = t / lanes_per_px;
+    const bool act = row < rows && c < C;
+    float s = 0.f;
+    if (act)
+      for (int64_t p = pbeg + row; p < pend; p += rows) s += bf2f(g[p * C + c]);
+    red[t] = s;
+    __syncthreads();
+    if (row == 0 && act) {
+      for (int r = 1; r < rows; ++r) s += red[r * lanes_per_px + t];
+      atomicAdd(db + c, s);
+    }
+    __syncthreads();
+  }
+}
+
+// Head: out[p][j] = scale * (b[j] + sum_c w[j][c] x[p][c]), j = 0, 1 (float32 out).
+__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* __restrict__ x, int C, const float* __restrict__ w,
+                                                  const float* __restrict__ b, float scale, float* __restrict__ out,
+                                                  int64_t P) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  float s0 = 0.f, s1 = 0.f;
+  for (int c = 0; c < C; c += 8) {
+    const u16x8 a = *(const u16x8*)(x + p * C + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float v = bf2f(a[e]);
+      s0 += w[c + e] * v;
+      s1 += w[C + c + e] * v;
+    }
+  }
+  out[2 * p] = scale * (b[0] + s0);
+  out[2 * p + 1] = scale * (b[1] + s1);
+}
+
+// Mean squared error of the head output against the target field, and the
+// head's backward: gx[p][c] = sum_j go[p][j] w[j][c] (bfloat16),
+// dw[j][c] += sum_p go[p][j] x[p][c], db[j] += sum_p go[p][j],
+// go = scale * 2 (out - target) / (2 P).  loss[0] += sum (out - target)^2 / (2 P).
+__global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x, int C, const float* __restrict__ w,
+                                                  float scale, const float* __restrict__ out,
+                                                  const float* __restrict__ target, int64_t P,
+                                                  uint16_t* __restrict__ gx, float* __restrict__ dw,
+                                                  float* __restrict__ db, double* __restrict__ loss) {
+  __shared__ float part[2][4][8];     // per-wave partial dw, 8 channels at a time
+  __shared__ double lred[256];
+  __shared__ float bred[2][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 256 + t;
+  const bool ok = p < P;
+  const double inv = 1.0 / (2.0 * (double)P);
+  float g0 = 0.f, g1 = 0.f;
+  double l = 0.0;
+  if (ok) {
+    const float e0 = out[2 * p] - target[2 * p], e1 = out[2 * p + 1] - target[2 * p + 1];
+    l = ((double)e0 * e0 + (double)e1 * e1) * inv;
+    g0 = (float)(2.0 * inv) * e0 * scale;
+    g1 = (float)(2.0 * inv) * e1 * scale;
+  }
+  lred[t] = l;
+  bred[0][t] = g0;
+  bred[1][t] = g1;
+  for (int c = 0; c < C; c += 8) {
+    u16x8 a;
+    if (ok) a = *(const u16x8*)(x + p * C + c);
+    else a = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    u16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = f2bf(g0 * w[c + e] + g1 * w[C + c + e]);
+    if (ok) *(u16x8*)(gx + p * C + c) = o;
+    // dw partials: reduce over the block's pixels, 8 channels at a time
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float v = bf2f(a[e]);
+      float s0 = g0 * v, s1 = g1 * v;
+      for (int d = 32; d >= 1; d >>= 1) {
+        s0 += __shfl_xor(s0, d, 64);
+        s1 += __shfl_xor(s1, d, 64);
+      }
+      if (lane == 0) {
+        part[0][wv][e] = s0;
+        part[1][wv][e] = s1;
+      }
+    }
+    __syncthreads();
+    if (t < 16) {
+      const int j = t >> 3, e = t & 7;
+      float s = 0.f;
+      for (int q = 0; q < 4; ++q) s += part[j][q][e];
+      atomicAdd(dw + j * C + c + e, s);
+    }
+    __syncthreads();
+  }
+  for (int d = 128; d >= 1; d >>= 1) {
+    if (t < d) {
+      lred[t] += lred[t + d];
+      bred[0][t] += bred[0][t + d];
+      bred[1][t] += bred[1][t + d];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (loss) atomicAdd(loss, lred[0]);
+    atomicAdd(db, bred[0][0]);
+    atomicAdd(db + 1, bred[1][0]);
+  }
+}
+
+// Adam with bias correction (Kingma and Ba): m, v float32.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bfloat16 copies of one conv layer's float32 weights W[o][k] (k = tap C_in + c):
+// wA = W as is, wT[c][tap' C_out + o] = W[o][(8 - tap') C_in + c].
+__global__ __launch_bounds__(256) void k_pack_w(const float* __restrict__ w, int Cin, int Cout,
+                                                uint16_t* __restrict__ wA, uint16_t* __restrict__ wT) {
+  const int64_t n = (int64_t)Cout * 9 * Cin;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int K = 9 * Cin;
+  const int o = (int)(i / K), k = (int)(i - (int64_t)o * K);
+  const int tap = k / Cin, c = k - tap * Cin;
+  const uint16_t v = f2bf(w[i]);
+  wA[i] = v;
+  if (wT) wT[(int64_t)c * 9 * Cout + (8 - tap) * Cout + o] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ x, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+bool conv3_supported(int Cin, int Cout) { return Cout % 32 == 0 && Cin >= 1; }
+
+void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, uint16_t* out, int Cout,
+                  int Bn, int H, int W, int relu, hipStream_t s) {
+  const int64_t P = (int64_t)Bn * H * W;
+  const unsigned gx = (unsigned)((P + 255) / 256);
+  const bool gen = Cin % 32 != 0;
+  if (Cout % 64 == 0) {
+    dim3 grid(gx, Cout / 64);
+    if (gen) hipLaunchKernelGGL((k_conv3<4, true>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    else hipLaunchKernelGGL((k_conv3<4, false>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+  } else {
+    dim3 grid(gx, Cout / 32);
+    if (gen) hipLaunchKernelGGL((k_conv3<2, true>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    else hipLaunchKernelGGL((k_conv3<2, false>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+  }
+}
+
+void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, int Bn, int H, int W,
+                        hipStream_t s) {
+  const int64_t P = (int64_t)Bn * H * W;
+  const int K = 9 * Cin;
+  const unsigned kt = (unsigned)((K + 127) / 128), ot = (unsigned)(Cout / 32);
+  // enough pixel splits to give the GPU ~4096 blocks, at least 256 pixels each
+  int64_t splits = 4096 / (int64_t)(kt * ot);
+  if (splits < 1) splits = 1;
+  int64_t ppb = (P + splits - 1) / splits;
+  if (ppb < 256) ppb = 256;
+  ppb = (ppb + kWgPix - 1) / kWgPix * kWgPix;
+  splits = (P + ppb - 1) / ppb;
+  dim3 grid(kt, ot, (unsigned)splits);
+  if (Cin % 8 == 0)
+    hipLaunchKernelGGL((k_conv3_wgrad<false>), grid, dim3(256), 0, s, in, Cin, g, Cout, dW, P, H, W, ppb);
+  else
+    hipLaunchKernelGGL((k_conv3_wgrad<true>), grid, dim3(256), 0, s, in, Cin, g, Cout, dW, P, H, W, ppb);
+}
+
+void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, s, x, y, n);
+}
+void launch_relu_mask(uint16_t* g, const uint16_t* act, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_mask, dim3(nblk(n / 8)), dim3(256), 0, s, g, act, n / 8);
+}
+void launch_pool(const uint16_t* x, uint16_t* y, int Bn, int H, int W, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool, dim3(nblk((int64_t)Bn * (H / 2) * (W / 2) * (C / 8))), dim3(256), 0, s, x, y, Bn, H, W, C);
+}
+void launch_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, uint16_t* cat, int Bn, int H, int W,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_upcat, dim3(nblk((int64_t)Bn * H * W * ((Cd + Cs) / 8))), dim3(256), 0, s, deep, Cd, skip, Cs,
+                     cat, Bn, H, W);
+}
+void launch_up_grad(const uint16_t* gcat, int Ccat, int Cd, uint16_t* gdeep, int Bn, int Ho, int Wo, hipStream_t s) {
+  hipLaunchKernelGGL(k_up_grad, dim3(nblk((int64_t)Bn * Ho * Wo * (Cd / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gdeep,
+                     Bn, Ho, Wo);
+}
+void launch_skip_grad(const uint16_t* gcat, int Ccat, int Cd, const uint16_t* gpool, uint16_t* gskip, int Cs, int Bn,
+                      int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_skip_grad, dim3(nblk((int64_t)Bn * H * W * (Cs / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gpool,
+                     gskip, Cs, Bn, H, W);
+}
+void launch_bias_grad(const uint16_t* g, int C, int64_t P, float* db, hipStream_t s) {
+  int64_t blocks = 1024;
+  int64_t ppb = (P + blocks - 1) / blocks;
+  if (ppb < 64) ppb = 64;
+  blocks = (P + ppb - 1) / ppb;
+  hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)blocks), dim3(256), 0, s, g, C, P, ppb, db);
+}
+void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, float* out, int64_t P,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, b, scale, out, P);
+}
+void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, const float* out, const float* target,
+                     int64_t P, uint16_t* gx, float* dw, float* db, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, scale, out, target, P, gx, dw, db, loss);
+}
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+void launch_pack_w(const float* w, int Cin, int Cout, uint16_t* wA, uint16_t* wT, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_w, dim3(nblk((int64_t)Cout * 9 * Cin)), dim3(256), 0, s, w, Cin, Cout, wA, wT);
+}
+void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n)), dim3(256), 0, s, x, n, v);
+}
+
+}  // namespace cgn

@@ -102,3 +102,38 @@ def test_move_points_bilinear():
     ex = np.clip(pts[:, 0] + 0.01 * pts[:, 0] * pts[:, 1] - 0.003 * pts[:, 0], 0, 1)
     ey = np.clip(pts[:, 1] + 0.002 + 0.004 * pts[:, 1], 0, 1)
     assert np.abs(out[:, 0] - ex).max() < 1e-15 and np.abs(out[:, 1] - ey).max() < 1e-15
+
+
+def test_warm_start_move_reproduces_affine_fields_and_extends_constantly():
+    G = 8
+    grid = oc.tracer_grid(G).reshape(G, G, 2)
+    assert np.allclose(grid[0, 0], [0.5 / G, 0.5 / G]) and np.allclose(grid[0, 1], [1.5 / G, 0.5 / G])
+    # affine field sampled at the centres
+    field = np.stack([0.02 * grid[..., 0] - 0.01 * grid[..., 1] + 0.003,
+                      -0.015 * grid[..., 0] + 0.01], axis=-1)
+    rng = np.random.default_rng(4)
+    inner = 0.5 / G + (1 - 1.0 / G) * rng.random((200, 2))
+    want = inner + np.stack([0.02 * inner[:, 0] - 0.01 * inner[:, 1] + 0.003,
+                             -0.015 * inner[:, 0] + 0.01], axis=1)
+    assert np.allclose(oc.warm_start_move(inner, field), want, atol=1e-15)
+    # beyond the outermost centres the field is held constant (corner value)
+    corner = np.array([[0.01, 0.02]])
+    assert np.allclose(oc.warm_start_move(corner, field), corner + field[0, 0], atol=1e-15)
+    # clamped to the unit square
+    big = np.full((G, G, 2), 5.0)
+    assert np.array_equal(oc.warm_start_move(inner, big), np.ones_like(inner))
+    # a single cell is a constant shift
+    assert np.allclose(oc.warm_start_move(inner, np.array([[[0.01, -0.02]]])), inner + [0.01, -0.02])
+
+
+def test_log_density_mean_is_zero_in_linear_space():
+    from synth import voronoi_map, lognormal_values
+    m = voronoi_map(1000, 32, 2000, fractal=False)
+    s = lognormal_values(1000, 32, 1.0)
+    labels, counts, _ = oc.rasterize(m.xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, 64)
+    ld = oc.log_density(labels, counts, s, b=1.0)
+    assert abs(np.exp(ld).mean() - 1.0) < 1e-12
+    # background pixels carry log(BDV / mean), region pixels log(s/o / mean)
+    lut, d0 = oc.density_lut(counts, s, 1.0)
+    mean = (lut[labels]).mean()
+    assert np.allclose(ld[labels == 0], np.log(d0 / mean))
