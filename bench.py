@@ -47,7 +47,71 @@ WORKLOADS = {
     "config3": dict(seed=3000, R=200, n=200000, fractal=True, sigma=1.0, N=2048, precision=3, T=64,
                     desc="200 fractal Voronoi regions (~200k vertices), 2048^2, 64 time steps of a geometric "
                          "random walk (step sigma 0.1), all steps batched (direct), FP64-accumulated integral images"),
+    "config4": dict(seed=4000, count=256, precision=1,
+                    desc="256 independent fractal Voronoi cartograms, textures 256^2-2048^2, 16-300 regions, "
+                         "lognormal sigma 0.5-2, ~500 R N/1024 vertices each, one launch per kernel per iteration "
+                         "for all instances, compensated FP32 integral images, each to its own stopping rule"),
 }
+
+
+def _uneven_map(spec):
+    from synth import lognormal_values, voronoi_map
+    m = voronoi_map(spec["seed"], spec["R"], spec["n_target"], fractal=True)
+    return m, lognormal_values(spec["seed"], spec["R"], spec["sigma"]).astype(np.float32)
+
+
+def run_uneven(a, B, ctx, torch):
+    """Config 4: an uneven batch of independent cartograms in one series call."""
+    import multiprocessing as mp
+    from synth import uneven_batch_specs
+    w = WORKLOADS["config4"]
+    specs = uneven_batch_specs(w["seed"], w["count"])
+    log("config4: generating", len(specs), "maps")
+    with mp.get_context("fork").Pool(16) as pool:
+        maps = pool.map(_uneven_map, specs, chunksize=4)
+    gms = [ctx.map_from(m) for m, s in maps]
+    descs = [dict(map=g, xy0=torch.from_numpy(m.xy32()).cuda(), N=sp["N"], values=torch.from_numpy(s).cuda(),
+                  precision=w["precision"]) for g, (m, s), sp in zip(gms, maps, specs)]
+    px = sum(sp["N"] ** 2 for sp in specs)
+    shape = ctx.autotune(2048, w["precision"], max(1, px // (2048 * 2048)))
+    ctx.step_series(descs, graph_iters=a.graph_iters)      # warm-up
+    torch.cuda.synchronize()
+    ctx.profile_stage(a.stage, a.profile_every)
+    t0 = time.perf_counter()
+    res = ctx.step_series(descs, graph_iters=a.graph_iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    stage_ms, stage_n = ctx.profile_read()
+    ctx.profile_stage(None)
+    iters = np.array([int(r["iters"][0]) for r in res], dtype=np.int64)
+    status = np.array([int(r["status"][0]) for r in res])
+    Ns = np.array([sp["N"] for sp in specs], dtype=np.int64)
+    # the same cartograms one per call (first 32), for the batching gain
+    k = 32
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for d in descs[:k]:
+        ctx.step_series([d], graph_iters=a.graph_iters)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t1) * 1e3
+    px_iter = float((Ns * Ns * iters).sum())
+    # achieved bytes of the timed kernel: an iteration's launch covers every
+    # instance still running; use the mean active pixel count per launch
+    roof = None
+    if a.stage in ("sat_final", "sat_reduce", "raster_fill") and stage_n:
+        # a launch covers the instances still running: mean algorithmic bytes per launch
+        per = sum(alg_bytes(a.stage, int(N), w["precision"], 0) * int(it) for N, it in zip(Ns, iters))
+        per /= max(int(iters.max()), 1)
+        ach = per / (stage_ms / stage_n * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel=a.stage, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=counter_traffic(a.stage, "config4"),
+                    avg_launch_us=stage_ms / stage_n * 1e3, launches=stage_n, alg_bytes_per_launch=per,
+                    note="bytes per launch = mean over the run's iterations of the instances still running")
+    return dict(workload=w["desc"], instances=len(specs), texture_mpx=px / 1e6, ms_batch=ms,
+                ms_per_cartogram=ms / len(specs), mpx_iter_per_s=px_iter / (ms / 1e3) / 1e6,
+                iterations_mean=float(iters.mean()), iterations_max=int(iters.max()),
+                converged=int((status == 0).sum()), stalled=int((status == 1).sum()), tile=list(shape),
+                single_calls_ms_per_cartogram=ms_single / k, single_calls_maps=k, roofline=roof)
 
 STORE_BYTES = {0: 4, 1: 4, 2: 8, 3: 4}  # stored table entry per precision (F32, COMP, F64, F64ACC)
 PREC_NAMES = ["F32", "COMP", "F64", "F64ACC"]
@@ -111,6 +175,28 @@ def roofline(stage, ms, n, N, prec, n_pts, instances, workload):
                 avg_launch_us=avg_ms * 1e3, launches=n, alg_bytes_per_launch=per)
 
 
+def run_learned(a, B, ctx, torch):
+    """Config 5: warm start by the trained net followed by the plain
+    iteration, against the plain method, on held-out seeded maps."""
+    from paper_2604_13880_amd import learned as Lr
+    path = os.path.join(ROOT, "paper_2604_13880_amd", "weights", "warm_start_512.bin")
+    if not os.path.exists(path):
+        return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
+    net = B.Net(ctx, max_batch=8, **Lr.NET_CFG)
+    net.load(path)
+    log("config5: generating", a.learned_maps, "held-out maps")
+    maps = Lr.make_maps(range(Lr.TEST_SEED0, Lr.TEST_SEED0 + a.learned_maps), workers=16)
+    rep = Lr.compare(ctx, net, maps, single=min(16, a.learned_maps), area_source=1)
+    rep["workload"] = ("held-out seeded maps, 50-150 fractal Voronoi regions (~250 vertices per region), "
+                       "lognormal sigma 1, 512^2, polygon-area density, to max area error < 1% or the stopping rule; "
+                       "warm side = log-density + one plain iteration + U-Net forward + graded warm start + plain "
+                       "iterations; 32 cartograms per call on both sides")
+    rep["speedup_learned_batched_vs_plain_single"] = rep["plain_single_ms_per_cartogram"] / rep["warm_ms_per_cartogram"]
+    rep["speedup_learned_batched_vs_plain_batched"] = rep["plain_ms_per_cartogram"] / rep["warm_ms_per_cartogram"]
+    net.close()
+    return rep
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -136,7 +222,8 @@ def cpu_baseline(m, values, N, gpu_iters, sample_iters):
 
 def precision_table(ctx, B, m, values, N):
     """Max |S - S64| / C and |T - T64| / C of the float-stored modes against
-    double accumulation and storage, on the map's density texture."""
+    double accumulation and storage, on the map's density texture, and the
+    position and max-area-error differences after 20 whole iterations."""
     import torch
     gm = ctx.map_from(m)
     lab, cnt, _ = ctx.rasterize(gm, torch.from_numpy(m.xy32()).cuda(), N)
@@ -154,6 +241,16 @@ def precision_table(ctx, B, m, values, N):
         eS = float((im.S[:, : N + 1].double() - ref.S[:, : N + 1]).abs().max()) / C
         eT = float((im.T[:, : N + 1].double() - ref.T[:, : N + 1]).abs().max()) / C
         out[name] = {"S_rel": eS, "T_rel": eT}
+    # whole iterations: positions and max area error after 20 iterations
+    # against the double-precision mode
+    xy0 = torch.from_numpy(m.xy32()).cuda()
+    vals = torch.from_numpy(np.asarray(values, np.float32)).cuda()
+    runs = {}
+    for name, prec in (("F64", B.F64), ("F32", B.F32), ("COMP", B.COMP), ("F64ACC", B.F64ACC)):
+        runs[name] = ctx.step_series([dict(map=gm, xy0=xy0, N=N, values=vals, precision=prec, fixed_iters=20)])[0]
+    for name in ("F32", "COMP", "F64ACC"):
+        out[name]["xy_20_iters_max_abs"] = float((runs[name]["xy"] - runs["F64"]["xy"]).abs().max())
+        out[name]["xi_20_iters_abs"] = abs(float(runs[name]["xi"][0]) - float(runs["F64"]["xi"][0]))
     return out
 
 
@@ -203,6 +300,9 @@ def main():
     ap.add_argument("--profile-every", type=int, default=8, help="time one launch of the stage per this many iterations")
     ap.add_argument("--no-series", action="store_true", help="skip the batched 64-step series (config 3)")
     ap.add_argument("--series-steps", type=int, default=1, help="timed repetitions of the batched series")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch (config 4)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start (config 5)")
+    ap.add_argument("--learned-maps", type=int, default=64, help="held-out maps of the learned comparison")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
     a = ap.parse_args()
@@ -264,6 +364,14 @@ def main():
     if not a.no_series and a.workload == "config2":
         series = run_series(a, WORKLOADS["config3"], B, ctx, torch)
 
+    uneven = None
+    if not a.no_uneven and a.workload == "config2":
+        uneven = run_uneven(a, B, ctx, torch)
+
+    learned = None
+    if not a.no_learned and a.workload == "config2":
+        learned = run_learned(a, B, ctx, torch)
+
     cpu = None
     if not a.no_cpu:
         log("cpu baseline", a.cpu_iters, "iterations")
@@ -279,6 +387,7 @@ def main():
         "status": ["converged", "stalled", "maxiter", "error"][status],
         "reached_tol": status == 0, "ms_per_iteration": ms_step / max(iters, 1),
         "tile": list(tile), "roofline": roof, "cpu_baseline": cpu, "batched_series": series,
+        "uneven_batch": uneven, "learned_warm_start": learned,
     }
     print(json.dumps(out), flush=True)
 

@@ -195,17 +195,20 @@ typedef struct {
   int32_t* flags;   /* HOST [T] CG_FLAG_* */
   double* eps;      /* HOST [T] final mean area error */
   double* xi;       /* HOST [T] final max area error */
+  float* warm_step; /* HOST [T] warm-start step taken (0: plain start), or NULL */
 } cg_series_out;
 
 /* Runs every series in desc[0..n_series); out[k] receives series k.
  * Warm start: with init_field, the starting positions (of the first step
- * in cumulative mode, of every step in direct mode) are first moved by
- * the field (bilinear between the grid's pixel centres, constant beyond
- * the outermost ones, clamped to the unit square).  The moved map is
- * rasterised and its max area error computed; if it folded (a pixel
- * centre claimed by two regions) or its error is not below that of the
- * plain start, the plain start is used instead and CG_FLAG_FALLBACK is
- * set for that step.  The plain iteration then runs as usual.
+ * in cumulative mode, of every step in direct mode) are moved by alpha
+ * times the field (bilinear between the grid's pixel centres, constant
+ * beyond the outermost ones, clamped to the unit square) for the trial
+ * steps alpha = 1, 3/4, 1/2, 1/4.  Each moved map is rasterised and its max
+ * area error computed; a step whose map folded (a pixel centre claimed by
+ * two regions) is rejected.  The run starts from the non-folding step
+ * with the lowest error if that error is below the plain start's, else
+ * from the plain start, with CG_FLAG_FALLBACK set for that step.  The
+ * plain iteration then runs as usual.
  * Blocking: starts after the work already queued on `stream` and
  * returns when all steps have stopped.  Iterations are issued
  * as captured HIP graphs of `graph_iters` iterations (0: default 8; a

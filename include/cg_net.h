@@ -16,8 +16,10 @@
  * bias, ReLU); 2x2 average pooling between encoder levels; the decoder
  * upsamples x2 (nearest), concatenates [upsampled, encoder skip] and
  * applies two 3x3 convolutions; a 1x1 head maps base_channels to 2 and
- * multiplies by out_scale.  Output = displacement (dx, dy) in units of
- * the unit square at the pixel centres of the input.
+ * multiplies by out_scale; with a residual gain g the output adds g times
+ * input channels 1 and 2 (a first estimate of the field given as input).
+ * Output = displacement (dx, dy) in units of the unit square at the pixel
+ * centres of the input.
  *
  * Parameter vector (float32, this order): for each 3x3 layer (enc0a,
  * enc0b, enc1a, ..., enc{L-1}b, dec{L-2}a, dec{L-2}b, ..., dec0a, dec0b)
@@ -48,6 +50,8 @@ typedef struct {
   int32_t max_batch;     /* largest batch passed to forward / backward */
   float out_scale;       /* head output multiplier */
   uint64_t seed;         /* weight initialisation (He normal, zero biases) */
+  int32_t in_channels;   /* input channels, 1..8 */
+  float residual_gain;   /* output += residual_gain * input channels 1, 2 (needs in_channels >= 3; 0 = off) */
 } cg_net_config;
 
 /* Create a net on the context's device; allocates weights, Adam moments,
@@ -65,7 +69,8 @@ int cg_net_set_params(cg_net* net, const float* src, void* stream);
 int cg_net_get_grads(cg_net* net, float* dst, void* stream);
 int cg_net_zero_grads(cg_net* net, void* stream);
 
-/* Forward pass: input float [B][H][W] (log of density over its mean),
+/* Forward pass: input float [B][H][W][in_channels] (channel 0: log of
+ * density over its mean; further channels as the caller's features),
  * output float [B][H][W][2] (dx, dy).  Keeps the activations for the next
  * cg_net_backward.  1 <= B <= max_batch. */
 int cg_net_forward(cg_net* net, const float* input, int32_t batch, float* out, void* stream);
@@ -98,6 +103,12 @@ int cg_log_density(cg_ctx* ctx, int N, const uint16_t* labels, const int64_t* co
  * centre (the displacement of tracers moved along by cg_step_series).
  * final and out float [G][G][2]. */
 int cg_tracer_field(cg_ctx* ctx, int32_t G, const float* final_xy, float* out, void* stream);
+
+/* Box average of a field over factor x factor cells: in float [G][G][2],
+ * out float [G/factor][G/factor][2] (factor divides G).  A coarser
+ * warm-start field moves neighbouring vertices more alike, which keeps
+ * small regions from folding. */
+int cg_field_pool(cg_ctx* ctx, int32_t G, const float* in, int32_t factor, float* out, void* stream);
 
 #ifdef __cplusplus
 }

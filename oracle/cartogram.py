@@ -319,6 +319,28 @@ def warm_start_move(xy: np.ndarray, field: np.ndarray) -> np.ndarray:
     return np.clip(xy + d, 0.0, 1.0)
 
 
+WARM_STEPS = (1.0, 0.75, 0.5, 0.25)
+
+
+def warm_start_choose(m, values, N: int, xy0: np.ndarray, field: np.ndarray):
+    """Graded warm start: among the trial steps alpha * field, keep the one
+    whose moved map has no pixel claimed by two regions and whose max area
+    error is lowest, if that error is below the plain start's.  Returns
+    (alpha, starting positions); alpha = 0 is the plain start."""
+    A = region_areas(xy0, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions)
+    best = cartographic_errors(A, values)[1]
+    pick = 0.0
+    for a in WARM_STEPS:
+        xy = warm_start_move(xy0, a * field)
+        _, _, conflicts = rasterize(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, N)
+        if conflicts > 0:
+            continue
+        xi = cartographic_errors(region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions), values)[1]
+        if xi < best:
+            best, pick = xi, a
+    return pick, (warm_start_move(xy0, pick * field) if pick else xy0.copy())
+
+
 def tracer_grid(G: int) -> np.ndarray:
     """Pixel centres ((i + 1/2)/G, (j + 1/2)/G), row-major over j, [G*G][2]."""
     c = (np.arange(G) + 0.5) / G

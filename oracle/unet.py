@@ -40,8 +40,9 @@ class Layer:
     b_off: int
 
 
-def layer_table(c: int, L: int):
-    """Conv layers in parameter order, head offsets, parameter count."""
+def layer_table(c: int, L: int, cin0: int = 1):
+    """Conv layers in parameter order, head offsets, parameter count
+    (cin0 input channels)."""
     layers, off = [], 0
 
     def add(cin, cout, level):
@@ -52,7 +53,7 @@ def layer_table(c: int, L: int):
         off += cout
 
     for l in range(L):
-        add(1 if l == 0 else c << (l - 1), c << l, l)
+        add(cin0 if l == 0 else c << (l - 1), c << l, l)
         add(c << l, c << l, l)
     for l in range(L - 2, -1, -1):
         add((c << (l + 1)) + (c << l), c << l, l)
@@ -78,11 +79,15 @@ def _up(x):
     return x.repeat_interleave(2, dim=2).repeat_interleave(2, dim=3)
 
 
-def forward(p, x, c: int, L: int, out_scale: float):
-    """x: [B][H][W] -> (out [B][H][W][2], cache).  All float64."""
-    layers, hw, hb, n = layer_table(c, L)
+def forward(p, x, c: int, L: int, out_scale: float, residual_gain: float = 0.0):
+    """x: [B][H][W] or [B][H][W][C] -> (out [B][H][W][2], cache).  All
+    float64.  With a residual gain g the output adds g * x[..., 1:3]."""
+    xa = np.asarray(x, dtype=np.float64)
+    if xa.ndim == 3:
+        xa = xa[..., None]
+    layers, hw, hb, n = layer_table(c, L, xa.shape[-1])
     assert len(p) == n
-    t = torch.from_numpy(np.asarray(x, dtype=np.float64))[:, None]
+    t = torch.from_numpy(xa).permute(0, 3, 1, 2).contiguous()
     cache = {"x": t, "in": [], "a": [], "e": [], "cat": [], "da": [], "d": []}
     li = 0
     src = t
@@ -109,7 +114,10 @@ def forward(p, x, c: int, L: int, out_scale: float):
     Wh = torch.from_numpy(np.asarray(p[hw:hw + 2 * c], dtype=np.float64)).reshape(2, c)
     bh = torch.from_numpy(np.asarray(p[hb:hb + 2], dtype=np.float64))
     out = out_scale * (torch.einsum("jc,bchw->bhwj", Wh, deep) + bh)
+    if residual_gain:
+        out = out + residual_gain * torch.from_numpy(xa[..., 1:3])
     cache["d0"] = deep
+    cache["resid"] = residual_gain * xa[..., 1:3] if residual_gain else 0.0
     return out.numpy(), cache
 
 
@@ -128,12 +136,14 @@ def _conv_backward(g, inp, w):
 
 def backward(p, cache, target, c: int, L: int, out_scale: float):
     """Loss (mean squared error) and the flat gradient, float64."""
-    layers, hw, hb, n = layer_table(c, L)
+    layers, hw, hb, n = layer_table(c, L, cache["x"].shape[1])
     grads = np.zeros(n, dtype=np.float64)
     Wh = torch.from_numpy(np.asarray(p[hw:hw + 2 * c], dtype=np.float64)).reshape(2, c)
     bh = torch.from_numpy(np.asarray(p[hb:hb + 2], dtype=np.float64))
     d0 = cache["d0"]
     out = out_scale * (torch.einsum("jc,bchw->bhwj", Wh, d0) + bh)
+    if not isinstance(cache["resid"], float):
+        out = out + torch.from_numpy(cache["resid"])
     tgt = torch.from_numpy(np.asarray(target, dtype=np.float64))
     diff = out - tgt
     loss = float((diff ** 2).mean())
@@ -173,10 +183,10 @@ def backward(p, cache, target, c: int, L: int, out_scale: float):
     return loss, grads
 
 
-def init_params(c: int, L: int, seed: int):
+def init_params(c: int, L: int, seed: int, cin0: int = 1):
     """He-normal weights and zero biases (numpy generator; the library's
     own initialisation uses its own seeded generator)."""
-    layers, hw, hb, n = layer_table(c, L)
+    layers, hw, hb, n = layer_table(c, L, cin0)
     rng = np.random.default_rng(seed)
     p = np.zeros(n, dtype=np.float64)
     for ly in layers:

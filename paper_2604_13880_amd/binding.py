@@ -42,13 +42,14 @@ class CgSeriesDesc(C.Structure):
 
 class CgNetConfig(C.Structure):
     _fields_ = [("base_channels", C.c_int32), ("levels", C.c_int32), ("height", C.c_int32),
-                ("width", C.c_int32), ("max_batch", C.c_int32), ("out_scale", C.c_float), ("seed", C.c_uint64)]
+                ("width", C.c_int32), ("max_batch", C.c_int32), ("out_scale", C.c_float), ("seed", C.c_uint64),
+                ("in_channels", C.c_int32), ("residual_gain", C.c_float)]
 
 
 class CgSeriesOut(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("extra_xy", C.c_void_p), ("frames", C.c_void_p),
                 ("iters", C.c_void_p), ("status", C.c_void_p), ("flags", C.c_void_p),
-                ("eps", C.c_void_p), ("xi", C.c_void_p)]
+                ("eps", C.c_void_p), ("xi", C.c_void_p), ("warm_step", C.c_void_p)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib():
             "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
             "cg_log_density": (C.c_int, [vp, C.c_int, vp, vp, vp, i32, C.c_float, vp, vp]),
             "cg_tracer_field": (C.c_int, [vp, i32, vp, vp, vp]),
+            "cg_field_pool": (C.c_int, [vp, i32, vp, i32, vp, vp]),
             "cg_net_create": (C.c_int, [vp, C.POINTER(CgNetConfig), C.POINTER(vp)]),
             "cg_net_destroy": (C.c_int, [vp]),
             "cg_net_n_params": (i64, [vp]),
@@ -108,7 +110,7 @@ def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
             "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
             "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
-            "cg_profile_read", "cg_log_density", "cg_tracer_field", "cg_net_create", "cg_net_destroy",
+            "cg_profile_read", "cg_log_density", "cg_tracer_field", "cg_field_pool", "cg_net_create", "cg_net_destroy",
             "cg_net_n_params", "cg_net_get_params", "cg_net_set_params", "cg_net_get_grads", "cg_net_zero_grads",
             "cg_net_forward", "cg_net_backward", "cg_net_adam_step", "cg_net_save", "cg_net_load"]
 
@@ -297,6 +299,14 @@ class Context:
         self._check(lib().cg_tracer_field(self.handle, int(G), _ptr(fin), _ptr(out), _stream()), "cg_tracer_field")
         return out
 
+    def field_pool(self, field, factor: int):
+        """Box average of a [G, G, 2] field over factor x factor cells."""
+        f = _dev(field, torch.float32)
+        G = int(f.shape[0])
+        out = torch.empty((G // factor, G // factor, 2), dtype=torch.float32, device="cuda")
+        self._check(lib().cg_field_pool(self.handle, G, _ptr(f), int(factor), _ptr(out), _stream()), "cg_field_pool")
+        return out
+
     def profile_stage(self, stage: str | None, every: int = 1):
         self._check(lib().cg_profile_stage(self.handle, (stage or "").encode(), int(every)), "cg_profile_stage")
 
@@ -349,6 +359,7 @@ class Context:
             fr = torch.empty((max(T - 1, 0), K - 1, n, 2), dtype=torch.float32, device="cuda") if K >= 2 else None
             host = {key: np.zeros(T, dtype=np.int32) for key in ("iters", "status", "flags")}
             host.update({key: np.zeros(T, dtype=np.float64) for key in ("eps", "xi")})
+            host["warm_step"] = np.zeros(T, dtype=np.float32)
             d = descs[k]
             d.map = m.handle
             d.xy0 = xy0.data_ptr()
@@ -372,7 +383,7 @@ class Context:
             o.xy = xy.data_ptr()
             o.extra_xy = 0 if exy is None else exy.data_ptr()
             o.frames = 0 if fr is None else fr.data_ptr()
-            for key in ("iters", "status", "flags", "eps", "xi"):
+            for key in ("iters", "status", "flags", "eps", "xi", "warm_step"):
                 setattr(o, key, host[key].ctypes.data)
             keep += [vals, xy0, extra, field, xy, exy, fr]
             results.append(dict(xy=xy, extra_xy=exy, frames=fr, **host))
@@ -386,10 +397,12 @@ class Net:
     library's own kernels."""
 
     def __init__(self, ctx: Context, base_channels: int = 32, levels: int = 4, height: int = 512,
-                 width: int = 512, max_batch: int = 8, out_scale: float = 0.1, seed: int = 0):
+                 width: int = 512, max_batch: int = 8, out_scale: float = 0.1, seed: int = 0,
+                 in_channels: int = 1, residual_gain: float = 0.0):
         self.ctx = ctx
         cfg = CgNetConfig(int(base_channels), int(levels), int(height), int(width), int(max_batch),
-                          float(out_scale), int(seed))
+                          float(out_scale), int(seed), int(in_channels), float(residual_gain))
+        self.in_channels = int(in_channels)
         h = C.c_void_p()
         ctx._check(lib().cg_net_create(ctx.handle, C.byref(cfg), C.byref(h)), "cg_net_create")
         self.handle = h
@@ -428,8 +441,11 @@ class Net:
         self.ctx._check(lib().cg_net_zero_grads(self.handle, _stream()), "cg_net_zero_grads")
 
     def forward(self, x, out=None) -> torch.Tensor:
+        """x: [B, H, W] (one channel) or [B, H, W, in_channels]."""
         x = _dev(x, torch.float32)
         B = int(x.shape[0])
+        if x.numel() != B * self.H * self.W * self.in_channels:
+            raise CartogramError(f"net input must hold {self.in_channels} channel(s) of {self.H}x{self.W}")
         if out is None:
             out = torch.empty((B, self.H, self.W, 2), dtype=torch.float32, device="cuda")
         self.ctx._check(lib().cg_net_forward(self.handle, _ptr(x), B, _ptr(out), _stream()), "cg_net_forward")

@@ -32,13 +32,14 @@ bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, int64_t ti
 bool sat_shape_supported(int tw, int th);
 void launch_density(const Batch& B, hipStream_t s);
 void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s);
-void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s);
+void launch_apply_field(const Batch& B, int64_t pt_blocks, float alpha, hipStream_t s);
 void launch_restore(const Batch& B, int64_t pt_blocks, hipStream_t s);
 void launch_log_density(const uint16_t* labels, const int64_t* counts, const float* values, int R, int N, float shape,
                         float* lut, float* out, hipStream_t s);
 void launch_tracer_field(int G, const float* fin, float* out, hipStream_t s);
+void launch_field_pool(int G, int f, const float* in, float* out, hipStream_t s);
 void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s);
-void launch_err(const Batch& B, int mode, hipStream_t s);
+void launch_err(const Batch& B, int mode, hipStream_t s, float alpha = 0.f);
 void launch_init(const Batch& B, int64_t pt_blocks, hipStream_t s);
 void launch_export(const Batch& B, int64_t* contested, double* eps_xi, hipStream_t s);
 void launch_frames(const float* a, const float* b, float* out, int64_t n, int K, hipStream_t s);
@@ -775,6 +776,16 @@ int cg_tracer_field(cg_ctx* c, int32_t G, const float* final_xy, float* out, voi
   return check_launch(c);
 }
 
+int cg_field_pool(cg_ctx* c, int32_t G, const float* in, int32_t factor, float* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (!in || !out || G < 1 || factor < 1 || G % factor != 0)
+    return fail(c, CG_EINVAL, "cg_field_pool: need in, out and a factor dividing G");
+  (void)hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  cgk::launch_field_pool(G, factor, in, out, st);
+  return check_launch(c);
+}
+
 int cg_tile_shape(const cg_ctx* c, int N, int precision, int64_t batch_pixels, int32_t* tw, int32_t* th) {
   if (!c || !tw || !th || !pow2_ok(N)) return CG_EINVAL;
   int a, b;
@@ -816,15 +827,22 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
   bool warm = false;
   for (auto& s : specs) warm = warm || s.init_field != nullptr;
   if (warm) {
-    // warm start: error of the plain start, move by the field, rasterise the
-    // moved map (fold check), judge it, restore the rejected ones
+    // warm start: error of the plain start, then trial steps alpha * field
+    // (each rasterised for the fold check and scored by its max area
+    // error), then the best non-folding step, or the plain start
+    static const float kAlphas[] = {1.0f, 0.75f, 0.5f, 0.25f};
     cgk::launch_areas(P.B, P.reg_blocks, st);
     cgk::launch_err(P.B, 2, st);
-    cgk::launch_apply_field(P.B, P.pt_blocks, st);
-    cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
-    cgk::launch_areas(P.B, P.reg_blocks, st);
-    cgk::launch_err(P.B, 3, st);
+    for (float a : kAlphas) {
+      cgk::launch_restore(P.B, P.pt_blocks, st);
+      cgk::launch_apply_field(P.B, P.pt_blocks, a, st);
+      cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+      cgk::launch_areas(P.B, P.reg_blocks, st);
+      cgk::launch_err(P.B, 3, st, a);
+    }
     cgk::launch_restore(P.B, P.pt_blocks, st);
+    cgk::launch_apply_field(P.B, P.pt_blocks, -1.f, st);
+    cgk::launch_err(P.B, 4, st);
   }
   cgk::launch_areas(P.B, P.reg_blocks, st);
   cgk::launch_err(P.B, 0, st);
@@ -906,6 +924,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     if (o.flags) o.flags[r.step] = hs[k].flags;
     if (o.eps) o.eps[r.step] = hs[k].eps;
     if (o.xi) o.xi[r.step] = hs[k].xi;
+    if (o.warm_step) o.warm_step[r.step] = hs[k].ws_alpha;
   }
   (void)desc;
   return CG_OK;

@@ -42,6 +42,9 @@ struct IterState {
   double xi, eps, best_xi;
   double d0, C;       // density parameters of the latest iteration
   double xi0;         // max error of the plain (not warm-started) start
+  double ws_best;     // lowest max error among the warm start's trial steps
+  float ws_alpha;     // chosen warm-start step (0: plain start)
+  int32_t pad1;
 };
 
 struct Inst {

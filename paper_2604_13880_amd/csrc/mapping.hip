@@ -162,16 +162,19 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   *ptr = o;
 }
 
-// Warm start: move every point by a displacement field given at the pixel
-// centres of a G x G grid ([G][G][2], centre (i + 1/2, j + 1/2) / G),
-// interpolated bilinearly (constant beyond the outermost centres), then
-// clamp to the unit square.
-__global__ __launch_bounds__(256) void k_apply_field(Batch B) {
+// Warm start: move every point by alpha times a displacement field given
+// at the pixel centres of a G x G grid ([G][G][2], centre (i + 1/2, j +
+// 1/2) / G), interpolated bilinearly (constant beyond the outermost
+// centres), then clamp to the unit square.  alpha < 0: the instance's
+// chosen step (IterState::ws_alpha; 0 = no move).
+__global__ __launch_bounds__(256) void k_apply_field(Batch B, float alpha) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
+  const float a = alpha < 0.f ? I.st->ws_alpha : alpha;
+  if (a == 0.f) return;
   float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
   const float2 p = *ptr;
   const int G = (int)I.init_G;
@@ -191,14 +194,14 @@ __global__ __launch_bounds__(256) void k_apply_field(Batch B) {
     dx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
     dy = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
   }
-  *ptr = make_float2(fminf(fmaxf(p.x + dx, 0.f), 1.f), fminf(fmaxf(p.y + dy, 0.f), 1.f));
+  *ptr = make_float2(fminf(fmaxf(p.x + a * dx, 0.f), 1.f), fminf(fmaxf(p.y + a * dy, 0.f), 1.f));
 }
 
-// Warm start rejected: put the starting positions back.
+// Warm start: put the starting positions back (before the next trial step).
 __global__ __launch_bounds__(256) void k_restore(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
-  if (I.init_field == nullptr || !(I.st->flags & CG_FLAG_FALLBACK)) return;
+  if (I.init_field == nullptr) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   if (idx < I.n_vert) {
@@ -246,6 +249,23 @@ __global__ __launch_bounds__(256) void k_log_density(const uint16_t* labels, con
   out[i] = v <= R ? lut[v] : lut[0];
 }
 
+// Box average of a [G][G][2] field over f x f cells -> [G/f][G/f][2].
+__global__ __launch_bounds__(256) void k_field_pool(int G, int f, const float2* in, float2* out) {
+  const int g = G / f;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)g * g) return;
+  const int j = (int)(idx / g), i = (int)(idx - (int64_t)j * g);
+  float sx = 0.f, sy = 0.f;
+  for (int b = 0; b < f; ++b)
+    for (int a = 0; a < f; ++a) {
+      const float2 v = in[(int64_t)(j * f + b) * G + i * f + a];
+      sx += v.x;
+      sy += v.y;
+    }
+  const float w = 1.f / (float)(f * f);
+  out[idx] = make_float2(sx * w, sy * w);
+}
+
 // Pixel-centre tracer grid, or the displacement of moved tracers from it.
 __global__ __launch_bounds__(256) void k_tracer_field(int G, const float2* fin, float2* out) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -280,11 +300,11 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
 
 // Cartographic errors and the stopping rule (Method, end of the static
 // construction).  mode 0: update the iteration state; mode 1: evaluate
-// only (eps, xi into the state, nothing else touched); mode 2: also keep
-// xi as the error of the plain start; mode 3: judge a warm start (instances
-// with a field): rejected, with CG_FLAG_FALLBACK, if the moved map folded
-// (contested pixels) or its error is not below the plain start's.
-__global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
+// only (eps, xi into the state, nothing else touched); modes 2-4 judge a
+// warm start (instances with a field): 2 keeps xi as the error of the plain
+// start, 3 records a trial step `alpha` if it is the best so far, 4 flags
+// CG_FLAG_FALLBACK when no trial step beat the plain start.
+__global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
@@ -314,8 +334,23 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode) {
   I.areas[0] = 1.0 - sa;
   st->xi = xi;
   st->eps = eps;
-  if (mode == 2) st->xi0 = xi;
-  if (mode == 3 && I.init_field != nullptr && (st->contested > 0 || !(xi < st->xi0))) st->flags |= CG_FLAG_FALLBACK;
+  if (mode == 2) {
+    st->xi0 = xi;
+    st->ws_best = xi;
+    st->ws_alpha = 0.f;
+  }
+  if (mode == 3 && I.init_field != nullptr) {
+    // a trial step of the warm start: kept if the moved map did not fold
+    // (no contested pixel, no overflowing crossing buffer) and its error is
+    // the lowest so far, below the plain start's
+    const int f = st->flags;
+    if (!(f & CG_FLAG_OVERFLOW) && st->contested == 0 && xi < st->ws_best) {
+      st->ws_best = xi;
+      st->ws_alpha = alpha;
+    }
+    st->flags = f & ~CG_FLAG_OVERFLOW;
+  }
+  if (mode == 4 && I.init_field != nullptr && st->ws_alpha == 0.f) st->flags |= CG_FLAG_FALLBACK;
   if (mode != 0) return;
   int it;
   if (!st->evaluated) {
@@ -398,8 +433,8 @@ void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s) {
   if (prec == CG_F64) hipLaunchKernelGGL(k_map_points<double>, dim3(pt_blocks), dim3(256), 0, s, B);
   else hipLaunchKernelGGL(k_map_points<float>, dim3(pt_blocks), dim3(256), 0, s, B);
 }
-void launch_apply_field(const Batch& B, int64_t pt_blocks, hipStream_t s) {
-  if (pt_blocks > 0) hipLaunchKernelGGL(k_apply_field, dim3(pt_blocks), dim3(256), 0, s, B);
+void launch_apply_field(const Batch& B, int64_t pt_blocks, float alpha, hipStream_t s) {
+  if (pt_blocks > 0) hipLaunchKernelGGL(k_apply_field, dim3(pt_blocks), dim3(256), 0, s, B, alpha);
 }
 void launch_restore(const Batch& B, int64_t pt_blocks, hipStream_t s) {
   if (pt_blocks > 0) hipLaunchKernelGGL(k_restore, dim3(pt_blocks), dim3(256), 0, s, B);
@@ -410,6 +445,11 @@ void launch_log_density(const uint16_t* labels, const int64_t* counts, const flo
   const int64_t n = (int64_t)N * N;
   hipLaunchKernelGGL(k_log_density, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, labels, lut, R, n, out);
 }
+void launch_field_pool(int G, int f, const float* in, float* out, hipStream_t s) {
+  const int64_t n = (int64_t)(G / f) * (G / f);
+  hipLaunchKernelGGL(k_field_pool, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, f, (const float2*)in,
+                     (float2*)out);
+}
 void launch_tracer_field(int G, const float* fin, float* out, hipStream_t s) {
   const int64_t n = (int64_t)G * G;
   hipLaunchKernelGGL(k_tracer_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, (const float2*)fin,
@@ -418,8 +458,8 @@ void launch_tracer_field(int G, const float* fin, float* out, hipStream_t s) {
 void launch_areas(const Batch& B, int64_t region_blocks, hipStream_t s) {
   if (region_blocks > 0) hipLaunchKernelGGL(k_areas, dim3(region_blocks), dim3(256), 0, s, B);
 }
-void launch_err(const Batch& B, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_err, dim3(B.n), dim3(256), 0, s, B, mode);
+void launch_err(const Batch& B, int mode, hipStream_t s, float alpha) {
+  hipLaunchKernelGGL(k_err, dim3(B.n), dim3(256), 0, s, B, mode, alpha);
 }
 void launch_init(const Batch& B, int64_t pt_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(pt_blocks), dim3(256), 0, s, B);

@@ -30,10 +30,11 @@ __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, u3
 // 3x3 convolution (stride 1, zero padding 1) as an implicit GEMM.
 // Block: 4 wavefronts x 64 pixels = 256 pixels, 16*MF output channels.
 // GEN = element-wise operand gathers (any C_in; used for C_in % 32 != 0).
-template <int MF, bool GEN>
+// F32OUT: float32 output (input gradients), else bfloat16.
+template <int MF, bool GEN, bool F32OUT>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, int Cin,
                                                const uint16_t* __restrict__ wA, const float* __restrict__ bias,
-                                               uint16_t* __restrict__ out, int Cout, int64_t P, int H, int W,
+                                               void* __restrict__ out, int Cout, int64_t P, int H, int W,
                                                int relu) {
   constexpr int NF = 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -131,14 +132,21 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
 #pragma unroll
     for (int m = 0; m < MF; ++m) {
       const int o = co0 + 16 * m + 4 * kq;
-      u16x4 tv;
+      f32x4 v4;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float v = acc[m][f][r] + (bias ? bias[o + r] : 0.f);
         if (relu) v = fmaxf(v, 0.f);
-        tv[r] = f2bf(v);
+        v4[r] = v;
       }
-      *(u16x4*)(out + p * Cout + o) = tv;
+      if (F32OUT) {
+        *(f32x4*)((float*)out + p * Cout + o) = v4;
+      } else {
+        u16x4 tv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[r] = f2bf(v4[r]);
+        *(u16x4*)((uint16_t*)out + p * Cout + o) = tv;
+      }
     }
   }
 }
@@ -257,16 +265,21 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ x, ui
   if (i < n) y[i] = f2bf(x[i]);
 }
 
-// g <- g where act > 0, else 0 (ReLU backward; act is the stored output)
-__global__ __launch_bounds__(256) void k_relu_mask(uint16_t* __restrict__ g, const uint16_t* __restrict__ act, int64_t n8) {
+// gm = g where act > 0, else 0 (ReLU backward; act is the stored output),
+// rounded once to bfloat16 for the matrix-core products that consume it
+__global__ __launch_bounds__(256) void k_relu_mask(const float* __restrict__ g, const uint16_t* __restrict__ act,
+                                                   uint16_t* __restrict__ gm, int64_t n8) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n8) return;
-  u16x8 gv = *(const u16x8*)(g + 8 * i);
+  const f32x4 g0 = *(const f32x4*)(g + 8 * i), g1 = *(const f32x4*)(g + 8 * i + 4);
   const u16x8 av = *(const u16x8*)(act + 8 * i);
+  u16x8 o;
 #pragma unroll
-  for (int e = 0; e < 8; ++e)
-    if (!(bf2f(av[e]) > 0.f)) gv[e] = 0;
-  *(u16x8*)(g + 8 * i) = gv;
+  for (int e = 0; e < 8; ++e) {
+    const float v = e < 4 ? g0[e] : g1[e - 4];
+    o[e] = bf2f(av[e]) > 0.f ? f2bf(v) : (uint16_t)0;
+  }
+  *(u16x8*)(gm + 8 * i) = o;
 }
 
 // 2x2 average pooling, [B][H][W][C] -> [B][H/2][W/2][C]
@@ -310,9 +323,9 @@ __global__ __launch_bounds__(256) void k_upcat(const uint16_t* __restrict__ deep
   *(u16x8*)(cat + p * (Cd + Cs) + c) = v;
 }
 
-// gdeep[b][y][x][c] = sum over the 2x2 children of gcat[..][c], c < Cd
-__global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ gcat, int Ccat, int Cd,
-                                                 uint16_t* __restrict__ gdeep, int Bn, int Ho, int Wo) {
+// gdeep[b][y][x][c] = sum over the 2x2 children of gcat[..][c], c < Cd (float32)
+__global__ __launch_bounds__(256) void k_up_grad(const float* __restrict__ gcat, int Ccat, int Cd,
+                                                 float* __restrict__ gdeep, int Bn, int Ho, int Wo) {
   const int C8 = Cd / 8;
   const int64_t n = (int64_t)Bn * Ho * Wo * C8;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -325,18 +338,19 @@ __global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ gc
   const int64_t b = r / Ho;
   const int W = 2 * Wo, H = 2 * Ho;
   const int64_t p = (b * H + 2 * yo) * W + 2 * xo;
-  const uint16_t* s = gcat + p * Ccat + c;
-  const u16x8 a0 = *(const u16x8*)s, a1 = *(const u16x8*)(s + Ccat), a2 = *(const u16x8*)(s + (int64_t)W * Ccat),
-              a3 = *(const u16x8*)(s + (int64_t)W * Ccat + Ccat);
-  u16x8 o;
+  const float* s = gcat + p * Ccat + c;
+  const int64_t dn = (int64_t)W * Ccat;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) o[e] = f2bf(bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e]));
-  *(u16x8*)(gdeep + i * 8) = o;
+  for (int h = 0; h < 2; ++h) {
+    const f32x4 a0 = *(const f32x4*)(s + 4 * h), a1 = *(const f32x4*)(s + Ccat + 4 * h),
+                a2 = *(const f32x4*)(s + dn + 4 * h), a3 = *(const f32x4*)(s + dn + Ccat + 4 * h);
+    *(f32x4*)(gdeep + i * 8 + 4 * h) = (a0 + a1) + (a2 + a3);
+  }
 }
 
-// gskip[b][y][x][c] = gcat[b][y][x][Cd + c] (if gcat) + gpool[b][y/2][x/2][c] / 4 (if gpool)
-__global__ __launch_bounds__(256) void k_skip_grad(const uint16_t* __restrict__ gcat, int Ccat, int Cd,
-                                                   const uint16_t* __restrict__ gpool, uint16_t* __restrict__ gskip,
+// gskip[b][y][x][c] = gcat[b][y][x][Cd + c] (if gcat) + gpool[b][y/2][x/2][c] / 4 (if gpool), float32
+__global__ __launch_bounds__(256) void k_skip_grad(const float* __restrict__ gcat, int Ccat, int Cd,
+                                                   const float* __restrict__ gpool, float* __restrict__ gskip,
                                                    int Cs, int Bn, int H, int W) {
   const int C8 = Cs / 8;
   const int64_t n = (int64_t)Bn * H * W * C8;
@@ -348,23 +362,13 @@ __global__ __launch_bounds__(256) void k_skip_grad(const uint16_t* __restrict__ 
   const int64_t r = p / W;
   const int y = (int)(r % H);
   const int64_t b = r / H;
-  float v[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = 0.f;
-  if (gcat) {
-    const u16x8 a = *(const u16x8*)(gcat + p * Ccat + Cd + c);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] += bf2f(a[e]);
+  for (int h = 0; h < 2; ++h) {
+    f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (gcat) v += *(const f32x4*)(gcat + p * Ccat + Cd + c + 4 * h);
+    if (gpool) v += 0.25f * *(const f32x4*)(gpool + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cs + c + 4 * h);
+    *(f32x4*)(gskip + p * Cs + c + 4 * h) = v;
   }
-  if (gpool) {
-    const u16x8 a = *(const u16x8*)(gpool + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cs + c);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] += 0.25f * bf2f(a[e]);
-  }
-  u16x8 o;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) o[e] = f2bf(v[e]);
-  *(u16x8*)(gskip + p * Cs + c) = o;
 }
 
 // bias gradient: db[c] += sum_p g[p][c]; block = 256 pixels-chunks x C channels
@@ -392,10 +396,12 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
   }
 }
 
-// Head: out[p][j] = scale * (b[j] + sum_c w[j][c] x[p][c]), j = 0, 1 (float32 out).
+// Head: out[p][j] = scale * (b[j] + sum_c w[j][c] x[p][c]) (+ gain *
+// resid[p][1 + j] when a residual input is given), j = 0, 1 (float32 out).
 __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* __restrict__ x, int C, const float* __restrict__ w,
-                                                  const float* __restrict__ b, float scale, float* __restrict__ out,
-                                                  int64_t P) {
+                                                  const float* __restrict__ b, float scale,
+                                                  const float* __restrict__ resid, int rc, float gain,
+                                                  float* __restrict__ out, int64_t P) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
   float s0 = 0.f, s1 = 0.f;
@@ -408,8 +414,13 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* __restrict__ x
       s1 += w[C + c + e] * v;
     }
   }
-  out[2 * p] = scale * (b[0] + s0);
-  out[2 * p + 1] = scale * (b[1] + s1);
+  float r0 = 0.f, r1 = 0.f;
+  if (resid) {
+    r0 = gain * resid[p * rc + 1];
+    r1 = gain * resid[p * rc + 2];
+  }
+  out[2 * p] = scale * (b[0] + s0) + r0;
+  out[2 * p + 1] = scale * (b[1] + s1) + r1;
 }
 
 // Mean squared error of the head output against the target field, and the
@@ -419,7 +430,7 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* __restrict__ x
 __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x, int C, const float* __restrict__ w,
                                                   float scale, const float* __restrict__ out,
                                                   const float* __restrict__ target, int64_t P,
-                                                  uint16_t* __restrict__ gx, float* __restrict__ dw,
+                                                  float* __restrict__ gx, float* __restrict__ dw,
                                                   float* __restrict__ db, double* __restrict__ loss) {
   __shared__ float part[2][4][8];     // per-wave partial dw, 8 channels at a time
   __shared__ double lred[256];
@@ -443,10 +454,15 @@ __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x
     u16x8 a;
     if (ok) a = *(const u16x8*)(x + p * C + c);
     else a = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    u16x8 o;
+    if (ok) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = f2bf(g0 * w[c + e] + g1 * w[C + c + e]);
-    if (ok) *(u16x8*)(gx + p * C + c) = o;
+      for (int h = 0; h < 2; ++h) {
+        f32x4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = g0 * w[c + 4 * h + e] + g1 * w[C + c + 4 * h + e];
+        *(f32x4*)(gx + p * C + c + 4 * h) = o;
+      }
+    }
     // dw partials: reduce over the block's pixels, 8 channels at a time
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -526,20 +542,31 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 bool conv3_supported(int Cin, int Cout) { return Cout % 32 == 0 && Cin >= 1; }
 
-void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, uint16_t* out, int Cout,
-                  int Bn, int H, int W, int relu, hipStream_t s) {
+template <bool F32OUT>
+static void conv3_t(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, void* out, int Cout, int Bn,
+                    int H, int W, int relu, hipStream_t s) {
   const int64_t P = (int64_t)Bn * H * W;
   const unsigned gx = (unsigned)((P + 255) / 256);
   const bool gen = Cin % 32 != 0;
   if (Cout % 64 == 0) {
     dim3 grid(gx, Cout / 64);
-    if (gen) hipLaunchKernelGGL((k_conv3<4, true>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
-    else hipLaunchKernelGGL((k_conv3<4, false>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    if (gen) hipLaunchKernelGGL((k_conv3<4, true, F32OUT>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    else hipLaunchKernelGGL((k_conv3<4, false, F32OUT>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
   } else {
     dim3 grid(gx, Cout / 32);
-    if (gen) hipLaunchKernelGGL((k_conv3<2, true>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
-    else hipLaunchKernelGGL((k_conv3<2, false>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    if (gen) hipLaunchKernelGGL((k_conv3<2, true, F32OUT>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
+    else hipLaunchKernelGGL((k_conv3<2, false, F32OUT>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
   }
+}
+
+void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, uint16_t* out, int Cout,
+                  int Bn, int H, int W, int relu, hipStream_t s) {
+  conv3_t<false>(in, Cin, wA, bias, out, Cout, Bn, H, W, relu, s);
+}
+
+void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* out, int Cout, int Bn, int H, int W,
+                      hipStream_t s) {
+  conv3_t<true>(in, Cin, wA, nullptr, out, Cout, Bn, H, W, 0, s);
 }
 
 void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, int Bn, int H, int W,
@@ -564,8 +591,8 @@ void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout
 void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, s, x, y, n);
 }
-void launch_relu_mask(uint16_t* g, const uint16_t* act, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_relu_mask, dim3(nblk(n / 8)), dim3(256), 0, s, g, act, n / 8);
+void launch_relu_mask(const float* g, const uint16_t* act, uint16_t* gm, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_mask, dim3(nblk(n / 8)), dim3(256), 0, s, g, act, gm, n / 8);
 }
 void launch_pool(const uint16_t* x, uint16_t* y, int Bn, int H, int W, int C, hipStream_t s) {
   hipLaunchKernelGGL(k_pool, dim3(nblk((int64_t)Bn * (H / 2) * (W / 2) * (C / 8))), dim3(256), 0, s, x, y, Bn, H, W, C);
@@ -575,11 +602,11 @@ void launch_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, ui
   hipLaunchKernelGGL(k_upcat, dim3(nblk((int64_t)Bn * H * W * ((Cd + Cs) / 8))), dim3(256), 0, s, deep, Cd, skip, Cs,
                      cat, Bn, H, W);
 }
-void launch_up_grad(const uint16_t* gcat, int Ccat, int Cd, uint16_t* gdeep, int Bn, int Ho, int Wo, hipStream_t s) {
+void launch_up_grad(const float* gcat, int Ccat, int Cd, float* gdeep, int Bn, int Ho, int Wo, hipStream_t s) {
   hipLaunchKernelGGL(k_up_grad, dim3(nblk((int64_t)Bn * Ho * Wo * (Cd / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gdeep,
                      Bn, Ho, Wo);
 }
-void launch_skip_grad(const uint16_t* gcat, int Ccat, int Cd, const uint16_t* gpool, uint16_t* gskip, int Cs, int Bn,
+void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, float* gskip, int Cs, int Bn,
                       int H, int W, hipStream_t s) {
   hipLaunchKernelGGL(k_skip_grad, dim3(nblk((int64_t)Bn * H * W * (Cs / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gpool,
                      gskip, Cs, Bn, H, W);
@@ -591,12 +618,12 @@ void launch_bias_grad(const uint16_t* g, int C, int64_t P, float* db, hipStream_
   blocks = (P + ppb - 1) / ppb;
   hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)blocks), dim3(256), 0, s, g, C, P, ppb, db);
 }
-void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, float* out, int64_t P,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, b, scale, out, P);
+void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, const float* resid,
+                     int rc, float gain, float* out, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, b, scale, resid, rc, gain, out, P);
 }
 void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, const float* out, const float* target,
-                     int64_t P, uint16_t* gx, float* dw, float* db, double* loss, hipStream_t s) {
+                     int64_t P, float* gx, float* dw, float* db, double* loss, hipStream_t s) {
   hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, scale, out, target, P, gx, dw, db, loss);
 }
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,

@@ -22,18 +22,20 @@ void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* 
 void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, int Bn, int H, int W,
                         hipStream_t s);
 void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s);
-void launch_relu_mask(uint16_t* g, const uint16_t* act, int64_t n, hipStream_t s);
+void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* out, int Cout, int Bn, int H, int W,
+                      hipStream_t s);
+void launch_relu_mask(const float* g, const uint16_t* act, uint16_t* gm, int64_t n, hipStream_t s);
 void launch_pool(const uint16_t* x, uint16_t* y, int Bn, int H, int W, int C, hipStream_t s);
 void launch_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, uint16_t* cat, int Bn, int H, int W,
                   hipStream_t s);
-void launch_up_grad(const uint16_t* gcat, int Ccat, int Cd, uint16_t* gdeep, int Bn, int Ho, int Wo, hipStream_t s);
-void launch_skip_grad(const uint16_t* gcat, int Ccat, int Cd, const uint16_t* gpool, uint16_t* gskip, int Cs, int Bn,
+void launch_up_grad(const float* gcat, int Ccat, int Cd, float* gdeep, int Bn, int Ho, int Wo, hipStream_t s);
+void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, float* gskip, int Cs, int Bn,
                       int H, int W, hipStream_t s);
 void launch_bias_grad(const uint16_t* g, int C, int64_t P, float* db, hipStream_t s);
-void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, float* out, int64_t P,
-                     hipStream_t s);
+void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, const float* resid,
+                     int rc, float gain, float* out, int64_t P, hipStream_t s);
 void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, const float* out, const float* target,
-                     int64_t P, uint16_t* gx, float* dw, float* db, double* loss, hipStream_t s);
+                     int64_t P, float* gx, float* dw, float* db, double* loss, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s);
 void launch_pack_w(const float* w, int Cin, int Cout, uint16_t* wA, uint16_t* wT, hipStream_t s);
@@ -51,7 +53,7 @@ struct Conv {
   uint16_t* wT = nullptr;    // bfloat16 [cin][9 cout], taps reversed (input gradient)
 };
 
-constexpr char kMagic[8] = {'C', 'G', 'N', 'E', 'T', '0', '0', '1'};
+constexpr char kMagic[8] = {'C', 'G', 'N', 'E', 'T', '0', '0', '2'};
 
 }  // namespace
 
@@ -70,9 +72,11 @@ struct cg_net {
   std::vector<uint16_t*> cat_l, da_l, d_l; // decoder (levels 0..L-2)
   float* out = nullptr;                    // head output [B][H][W][2] of the last forward
   int lastB = 0;
-  // gradient scratch
-  uint16_t *GA = nullptr, *GB = nullptr, *GC = nullptr;
-  std::vector<uint16_t*> gskip;
+  // gradient scratch: float32 gradients between layers, one bfloat16
+  // buffer for the masked gradient that the matrix-core products consume
+  float *GA = nullptr, *GB = nullptr, *GC = nullptr;
+  uint16_t* GM = nullptr;
+  std::vector<float*> gskip;
 };
 
 namespace {
@@ -121,6 +125,9 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
     return fail(ctx, CG_EINVAL, "cg_net_create: height and width must be multiples of 2^(levels-1), <= 8192");
   if (cfg->max_batch < 1) return fail(ctx, CG_EINVAL, "cg_net_create: max_batch must be >= 1");
   if (!std::isfinite(cfg->out_scale)) return fail(ctx, CG_EINVAL, "cg_net_create: bad out_scale");
+  if (cfg->in_channels < 1 || cfg->in_channels > 8) return fail(ctx, CG_EINVAL, "cg_net_create: in_channels must be 1..8");
+  if (!std::isfinite(cfg->residual_gain) || (cfg->residual_gain != 0.f && cfg->in_channels < 3))
+    return fail(ctx, CG_EINVAL, "cg_net_create: a residual gain needs in_channels >= 3");
   HIP_OK(ctx, hipSetDevice(ctx->device));
   cg_net* n = new cg_net();
   n->ctx = ctx;
@@ -144,7 +151,7 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
     n->conv.push_back(cv);
   };
   for (int l = 0; l < L; ++l) {
-    add(l == 0 ? 1 : ch(n, l - 1), ch(n, l), l);
+    add(l == 0 ? cfg->in_channels : ch(n, l - 1), ch(n, l), l);
     add(ch(n, l), ch(n, l), l);
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -172,7 +179,7 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
   }
   const int64_t B = n->maxB;
   auto act = [&](int l, int C) { return sizeof(uint16_t) * (size_t)B * hl(n, l) * wl(n, l) * C; };
-  A(act(0, 1), (void**)&n->x_in);
+  A(act(0, cfg->in_channels), (void**)&n->x_in);
   n->in_l.assign(L, nullptr);
   n->a_l.assign(L, nullptr);
   n->e_l.assign(L, nullptr);
@@ -191,14 +198,15 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
       A(act(l, cc), (void**)&n->cat_l[l]);
       A(act(l, ch(n, l)), (void**)&n->da_l[l]);
       A(act(l, ch(n, l)), (void**)&n->d_l[l]);
-      A(act(l, ch(n, l)), (void**)&n->gskip[l]);
+      A(2 * act(l, ch(n, l)), (void**)&n->gskip[l]);
       gmax = std::max(gmax, act(l, cc));
     }
   }
   A(sizeof(float) * (size_t)B * n->H * n->W * 2, (void**)&n->out);
-  A(gmax, (void**)&n->GA);
-  A(gmax, (void**)&n->GB);
-  A(gmax, (void**)&n->GC);
+  A(2 * gmax, (void**)&n->GA);
+  A(2 * gmax, (void**)&n->GB);
+  A(2 * gmax, (void**)&n->GC);
+  A(gmax, (void**)&n->GM);
   if (rc != CG_OK) {
     net_free(n);
     delete n;
@@ -285,7 +293,7 @@ int cg_net_forward(cg_net* n, const float* input, int32_t B, float* out, void* s
   (void)hipSetDevice(n->ctx->device);
   hipStream_t st = pick_stream(n->ctx, stream);
   const int L = n->L;
-  cgn::launch_to_bf16(input, n->x_in, (int64_t)B * n->H * n->W, st);
+  cgn::launch_to_bf16(input, n->x_in, (int64_t)B * n->H * n->W * n->cfg.in_channels, st);
   size_t li = 0;
   for (int l = 0; l < L; ++l) {
     const int h = hl(n, l), w = wl(n, l);
@@ -310,7 +318,9 @@ int cg_net_forward(cg_net* n, const float* input, int32_t B, float* out, void* s
     deep = n->d_l[l];
   }
   const int64_t P = (int64_t)B * n->H * n->W;
-  cgn::launch_head_fwd(deep, n->c, n->params + n->head_w, n->params + n->head_b, n->cfg.out_scale, n->out, P, st);
+  cgn::launch_head_fwd(deep, n->c, n->params + n->head_w, n->params + n->head_b, n->cfg.out_scale,
+                       n->cfg.residual_gain != 0.f ? input : nullptr, n->cfg.in_channels, n->cfg.residual_gain, n->out,
+                       P, st);
   HIP_OK(n->ctx, hipMemcpyAsync(out, n->out, sizeof(float) * P * 2, hipMemcpyDeviceToDevice, st));
   n->lastB = B;
   return check(n);
@@ -330,27 +340,25 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
   cgn::launch_head_bwd(d0, n->c, n->params + n->head_w, n->cfg.out_scale, n->out, target, P0, n->GA,
                        G + n->head_w, G + n->head_b, loss, st);
   // decoder, from level 0 upwards; conv index of dec level l: 2L + 2 (L-2-l)
-  uint16_t* gdeep = n->GA;
   for (int l = 0; l <= L - 2; ++l) {
     const int h = hl(n, l), w = wl(n, l);
     const int64_t P = (int64_t)B * h * w;
     const Conv& ca = n->conv[2 * L + 2 * (L - 2 - l)];
     const Conv& cb = n->conv[2 * L + 2 * (L - 2 - l) + 1];
-    // d = relu(conv_b(da))
-    cgn::launch_relu_mask(gdeep, n->d_l[l], P * cb.cout, st);
-    cgn::launch_conv3_wgrad(n->da_l[l], cb.cin, gdeep, cb.cout, G + cb.w_off, B, h, w, st);
-    cgn::launch_bias_grad(gdeep, cb.cout, P, G + cb.b_off, st);
-    cgn::launch_conv3(gdeep, cb.cout, cb.wT, nullptr, n->GB, cb.cin, B, h, w, 0, st);
+    // d = relu(conv_b(da)); GA holds the gradient of d
+    cgn::launch_relu_mask(n->GA, n->d_l[l], n->GM, P * cb.cout, st);
+    cgn::launch_conv3_wgrad(n->da_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, B, h, w, st);
+    cgn::launch_bias_grad(n->GM, cb.cout, P, G + cb.b_off, st);
+    cgn::launch_conv3_f32(n->GM, cb.cout, cb.wT, n->GB, cb.cin, B, h, w, st);
     // da = relu(conv_a(cat))
-    cgn::launch_relu_mask(n->GB, n->da_l[l], P * ca.cout, st);
-    cgn::launch_conv3_wgrad(n->cat_l[l], ca.cin, n->GB, ca.cout, G + ca.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GB, ca.cout, P, G + ca.b_off, st);
-    cgn::launch_conv3(n->GB, ca.cout, ca.wT, nullptr, n->GC, ca.cin, B, h, w, 0, st);
+    cgn::launch_relu_mask(n->GB, n->da_l[l], n->GM, P * ca.cout, st);
+    cgn::launch_conv3_wgrad(n->cat_l[l], ca.cin, n->GM, ca.cout, G + ca.w_off, B, h, w, st);
+    cgn::launch_bias_grad(n->GM, ca.cout, P, G + ca.b_off, st);
+    cgn::launch_conv3_f32(n->GM, ca.cout, ca.wT, n->GC, ca.cin, B, h, w, st);
     // cat = [up(deep), e_l]
     const int Cd = ch(n, l + 1), Cs = ch(n, l);
     cgn::launch_skip_grad(n->GC, Cd + Cs, Cd, nullptr, n->gskip[l], Cs, B, h, w, st);
     cgn::launch_up_grad(n->GC, Cd + Cs, Cd, n->GA, B, hl(n, l + 1), wl(n, l + 1), st);
-    gdeep = n->GA;
   }
   // encoder, from the deepest level down; GA holds the gradient of e_{L-1}
   for (int l = L - 1; l >= 0; --l) {
@@ -360,15 +368,15 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
     const Conv& cb = n->conv[2 * l + 1];
     if (l < L - 1)  // e_l feeds the decoder skip and the pooled input of level l+1 (gradient in GC)
       cgn::launch_skip_grad(n->gskip[l], ch(n, l), 0, n->GC, n->GA, ch(n, l), B, h, w, st);
-    cgn::launch_relu_mask(n->GA, n->e_l[l], P * cb.cout, st);
-    cgn::launch_conv3_wgrad(n->a_l[l], cb.cin, n->GA, cb.cout, G + cb.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GA, cb.cout, P, G + cb.b_off, st);
-    cgn::launch_conv3(n->GA, cb.cout, cb.wT, nullptr, n->GB, cb.cin, B, h, w, 0, st);
-    cgn::launch_relu_mask(n->GB, n->a_l[l], P * ca.cout, st);
+    cgn::launch_relu_mask(n->GA, n->e_l[l], n->GM, P * cb.cout, st);
+    cgn::launch_conv3_wgrad(n->a_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, B, h, w, st);
+    cgn::launch_bias_grad(n->GM, cb.cout, P, G + cb.b_off, st);
+    cgn::launch_conv3_f32(n->GM, cb.cout, cb.wT, n->GB, cb.cin, B, h, w, st);
+    cgn::launch_relu_mask(n->GB, n->a_l[l], n->GM, P * ca.cout, st);
     const uint16_t* src = l == 0 ? n->x_in : n->in_l[l];
-    cgn::launch_conv3_wgrad(src, ca.cin, n->GB, ca.cout, G + ca.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GB, ca.cout, P, G + ca.b_off, st);
-    if (l > 0) cgn::launch_conv3(n->GB, ca.cout, ca.wT, nullptr, n->GC, ca.cin, B, h, w, 0, st);
+    cgn::launch_conv3_wgrad(src, ca.cin, n->GM, ca.cout, G + ca.w_off, B, h, w, st);
+    cgn::launch_bias_grad(n->GM, ca.cout, P, G + ca.b_off, st);
+    if (l > 0) cgn::launch_conv3_f32(n->GM, ca.cout, ca.wT, n->GC, ca.cin, B, h, w, st);
   }
   return check(n);
 }
@@ -396,10 +404,11 @@ int cg_net_save(cg_net* n, const char* path) {
   {
     std::ofstream f(tmp, std::ios::binary);
     if (!f) return fail(n->ctx, CG_EINVAL, std::string("cg_net_save: cannot write ") + tmp);
-    const int32_t hdr[5] = {n->cfg.base_channels, n->cfg.levels, n->cfg.height, n->cfg.width, 0};
+    const int32_t hdr[5] = {n->cfg.base_channels, n->cfg.levels, n->cfg.height, n->cfg.width, n->cfg.in_channels};
     f.write(kMagic, 8);
     f.write((const char*)hdr, sizeof(hdr));
     f.write((const char*)&n->cfg.out_scale, sizeof(float));
+    f.write((const char*)&n->cfg.residual_gain, sizeof(float));
     const int64_t np = n->n_params;
     f.write((const char*)&np, sizeof(np));
     f.write((const char*)h.data(), sizeof(float) * h.size());
@@ -416,19 +425,22 @@ int cg_net_load(cg_net* n, const char* path) {
   if (!f) return fail(n->ctx, CG_EINVAL, std::string("cg_net_load: cannot read ") + path);
   char mg[8];
   int32_t hdr[5];
-  float sc = 0.f;
+  float sc = 0.f, gain = 0.f;
   int64_t np = 0;
   f.read(mg, 8);
   f.read((char*)hdr, sizeof(hdr));
   f.read((char*)&sc, sizeof(sc));
+  f.read((char*)&gain, sizeof(gain));
   f.read((char*)&np, sizeof(np));
   if (!f || memcmp(mg, kMagic, 8) != 0) return fail(n->ctx, CG_EINVAL, "cg_net_load: not a net file");
-  if (hdr[0] != n->cfg.base_channels || hdr[1] != n->cfg.levels || np != n->n_params)
+  if (hdr[0] != n->cfg.base_channels || hdr[1] != n->cfg.levels || hdr[4] != n->cfg.in_channels ||
+      np != n->n_params)
     return fail(n->ctx, CG_EINVAL, "cg_net_load: architecture differs from the net's");
   std::vector<float> h((size_t)np);
   f.read((char*)h.data(), sizeof(float) * h.size());
   if (!f) return fail(n->ctx, CG_EINVAL, "cg_net_load: truncated file");
   n->cfg.out_scale = sc;
+  n->cfg.residual_gain = gain;
   HIP_OK(n->ctx, hipDeviceSynchronize());
   HIP_OK(n->ctx, hipMemcpy(n->params, h.data(), sizeof(float) * np, hipMemcpyHostToDevice));
   hipStream_t st = n->ctx->stream;

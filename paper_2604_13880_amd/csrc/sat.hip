@@ -14,8 +14,9 @@
 //
 // Three passes over tiles of TW columns x TH rows (one block of TW threads
 // per tile), reduce-then-scan:
-//   k_sat_reduce  per tile: row totals, column prefix sums, cumulative
-//                 masses along anti-diagonals and diagonals
+//   k_sat_reduce  per tile: row totals, column prefix sums, and masses
+//                 below every anti-diagonal and diagonal (from line sums
+//                 of the raw densities, no row scans)
 //   k_sat_carry1  row carries across tile columns, tile-row prefix totals
 //   k_sat_carry2  carries entering every tile row for S, TA, TB; HA, HB
 //   k_sat_final   per tile with a TH-column halo on each side: row prefix
@@ -107,6 +108,52 @@ __device__ __forceinline__ void sub_band_scan(const float (*ds)[W], A (*Ms)[W], 
   }
 }
 
+__device__ __forceinline__ float shfl_xor_acc(float v, int d) { return __shfl_xor(v, d, 64); }
+__device__ __forceinline__ double shfl_xor_acc(double v, int d) { return __shfl_xor(v, d, 64); }
+__device__ __forceinline__ Comp shfl_xor_acc(Comp v, int d) {
+  return Comp{__shfl_xor(v.hi, d, 64), __shfl_xor(v.lo, d, 64)};
+}
+
+// Sum over the wavefront (butterfly: every lane gets the same value).
+template <typename A>
+__device__ __forceinline__ A wave_sum(A v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const A o = shfl_xor_acc(v, d);
+    acc_addv(v, o);
+  }
+  return v;
+}
+
+// Exclusive scan over the block's threads in thread order (fixed order);
+// `total` receives the block sum.  wt: LDS scratch of NW entries.
+template <typename A, int NW>
+__device__ __forceinline__ A block_exclusive_scan(A v, A* wt, A& total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const A ex = wave_exclusive_scan(v, lane);
+  A inc = ex;
+  acc_addv(inc, v);
+  __syncthreads();
+  if (lane == 63) wt[w] = inc;
+  __syncthreads();
+  A pre;
+  acc_zero(pre);
+  acc_zero(total);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if (i < w) acc_addv(pre, wt[i]);
+    acc_addv(total, wt[i]);
+  }
+  acc_addv(pre, ex);
+  return pre;
+}
+
+// Tile aggregates from line sums of the raw densities (no row scans):
+// column totals, row totals, and the sums h_a(s) over the tile's
+// anti-diagonals s = (p - x0) + (q - y0) and h_b(s) over its diagonals
+// s = (p - x0) - (q - y0) + TH - 1.  The mass of the tile below an
+// anti-diagonal slot c (pixels bisected by it count half) is then
+// sum_{s<c} h_a(s) + h_a(c)/2, and likewise for the diagonals.
 template <int P, int TW, int TH, bool DENSE>
 __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   typedef typename PT<P>::acc A;
@@ -116,13 +163,13 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int k = find_inst(B.off_tiles, B.n, b);
   const Inst I = B.inst[k];  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  constexpr int NW = TW / 64, D = TW + TH - 1, SB = kSub_Rows;
+  constexpr int NW = TW / 64, D = TW + TH - 1, SB = kSub_Rows, E = TW / 64;
+  static_assert(TH <= TW, "tiles are at least as wide as they are tall");
   __shared__ float ds[SB][TW];
-  __shared__ A Ms[SB][TW];
-  __shared__ A rt[SB];
-  __shared__ A zero4[SB];
+  __shared__ A rsum[TH];
+  __shared__ A wt[NW];
   __shared__ float lut_s[kLutLds];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int tile = (int)(b - B.off_tiles[k]);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
@@ -130,58 +177,66 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
   if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  if (t < SB) acc_zero(zero4[t]);
-  Cy* agg = (Cy*)I.agg;
-  const int64_t tid = (int64_t)ty * L.ntx + tx;
-  // per-thread partial aggregates: column prefix (c = t+1), two anti-diagonal
-  // and two diagonal cumulative masses (c = t, t+TW), the tile total
-  A col, sa0, sa1, sb0, sb1, tot;
-  acc_zero(col); acc_zero(sa0); acc_zero(sa1); acc_zero(sb0); acc_zero(sb1); acc_zero(tot);
+  A col, ha0, ha1, hb0, hb1;
+  acc_zero(col); acc_zero(ha0); acc_zero(ha1); acc_zero(hb0); acc_zero(hb1);
   const int c1 = t + TW;
   const bool has1 = c1 < D;
   for (int r0 = 0; r0 < TH; r0 += SB) {
     __syncthreads();
     stage_density<DENSE, SB, TW, TW>(I, lut_s, lut_lds, x0, y0 + r0, ds);
     __syncthreads();
-    sub_band_scan<A, TW, NW>(ds, Ms, zero4, 0, rt);
-    __syncthreads();
+    for (int rr = w; rr < SB; rr += NW) {   // row totals, one wavefront per row
+      A v;
+      acc_zero(v);
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc_add(v, ds[rr][lane + 64 * e]);
+      v = wave_sum(v);
+      if (lane == 0) rsum[r0 + rr] = v;
+    }
+#pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr;
-      const A rowT = rt[rr];
-      if (t == 0) {
-        agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rowT);
-        acc_addv(tot, rowT);
-      }
-      // R(x0 + t + 1) = M(t+1) - d(t+1)/2, or the row total at the right edge
-      if (t + 1 < TW) {
-        A v = Ms[rr][t + 1];
-        acc_add(v, -0.5f * ds[rr][t + 1]);
-        acc_addv(col, v);
-      } else {
-        acc_addv(col, rowT);
-      }
-      int ca = t - r;              // anti-diagonal u = x0+y0+c meets row y0+r at column x0+c-r
-      if (ca >= TW) acc_addv(sa0, rowT); else if (ca >= 0) acc_addv(sa0, Ms[rr][ca]);
-      int cb = t + r - TH + 1;     // diagonal v = x0-y0-TH+1+c meets it at column x0+c+r-TH+1
-      if (cb >= TW) acc_addv(sb0, rowT); else if (cb >= 0) acc_addv(sb0, Ms[rr][cb]);
-      if (has1) {
-        ca = c1 - r;
-        if (ca >= TW) acc_addv(sa1, rowT); else if (ca >= 0) acc_addv(sa1, Ms[rr][ca]);
-        cb = c1 + r - TH + 1;
-        if (cb >= TW) acc_addv(sb1, rowT); else if (cb >= 0) acc_addv(sb1, Ms[rr][cb]);
+      acc_add(col, ds[rr][t]);
+      const int ca = t - r;                 // anti-diagonal slot t meets row r here
+      if (ca >= 0) acc_add(ha0, ds[rr][ca]);
+      const int cb = t + r - TH + 1;        // diagonal slot t
+      if (cb >= 0) acc_add(hb0, ds[rr][cb]);
+      if (has1) {                           // slots t + TW (always right of column 0)
+        const int ca1 = c1 - r, cb1 = c1 + r - TH + 1;
+        if (ca1 < TW) acc_add(ha1, ds[rr][ca1]);
+        if (cb1 < TW) acc_add(hb1, ds[rr][cb1]);
       }
     }
   }
-  agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(col);
+  __syncthreads();
+  Cy* agg = (Cy*)I.agg;
+  const int64_t tid = (int64_t)ty * L.ntx + tx;
+  for (int r = t; r < TH; r += TW) agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rsum[r]);
+  A tot, tA0, tA1, tB0, tB1, z;
+  acc_zero(z);
+  A ex = block_exclusive_scan<A, NW>(col, wt, tot);
+  acc_addv(ex, col);
+  agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(ex);
   if (t == 0) {
     agg[L.colsum + tid * (TW + 1)] = (Cy)0;
     agg[L.tileTot + tid] = to_carry(tot);
   }
-  agg[L.cdfA + tid * D + t] = to_carry(sa0);
-  agg[L.cdfB + tid * D + t] = to_carry(sb0);
+  A ea0 = block_exclusive_scan<A, NW>(ha0, wt, tA0);
+  A ea1 = block_exclusive_scan<A, NW>(has1 ? ha1 : z, wt, tA1);
+  A eb0 = block_exclusive_scan<A, NW>(hb0, wt, tB0);
+  A eb1 = block_exclusive_scan<A, NW>(has1 ? hb1 : z, wt, tB1);
+  acc_addv(ea0, acc_half(ha0));
+  acc_addv(eb0, acc_half(hb0));
+  agg[L.cdfA + tid * D + t] = to_carry(ea0);
+  agg[L.cdfB + tid * D + t] = to_carry(eb0);
   if (has1) {
-    agg[L.cdfA + tid * D + c1] = to_carry(sa1);
-    agg[L.cdfB + tid * D + c1] = to_carry(sb1);
+    A a1 = tA0, b1 = tB0;
+    acc_addv(a1, ea1);
+    acc_addv(a1, acc_half(ha1));
+    acc_addv(b1, eb1);
+    acc_addv(b1, acc_half(hb1));
+    agg[L.cdfA + tid * D + c1] = to_carry(a1);
+    agg[L.cdfB + tid * D + c1] = to_carry(b1);
   }
 }
 

@@ -360,3 +360,37 @@ def test_integral_image_labels_2048(ctx, prec, shape):
     j, i = np.unravel_index(np.argmax(err), err.shape)
     say("  worst S at row", j, "col", i, "err/C", err[j, i] / ref.C)
     _cmp_inim(im, ref, prec, N)
+
+
+def test_uneven_batch_equals_single_runs_and_oracle(ctx):
+    """Independent cartograms of different sizes in one call (one launch
+    per kernel per iteration for all of them, each with its own stopping
+    rule) give exactly the results of one call per cartogram under the
+    same tile shape, and one batched iteration matches the oracle."""
+    import torch
+    specs = [(4100, 16, 64, 0.5, 40), (4101, 40, 256, 1.0, 25), (4102, 24, 128, 2.0, 60), (4103, 70, 512, 1.5, 33),
+             (4104, 16, 16, 0.8, 12), (4105, 33, 256, 1.2, 47)]
+    maps, descs = [], []
+    for seed, R, N, sig, cap in specs:
+        m = voronoi_map(seed, R, 40 * R, fractal=True)
+        s = lognormal_values(seed, R, sig).astype(np.float32)
+        maps.append((m, s, N))
+        descs.append(dict(map=ctx.map_from(m), xy0=m.xy32(), N=N, values=s, precision=1, max_iters=cap, patience=16))
+    px = sum(N * N for _, _, N in maps)
+    for N in {N for _, _, N in maps}:
+        ctx.set_tile_shape(N, 1, N * N, 64, 16)
+    ctx.set_tile_shape(512, 1, px, 64, 16)
+    say("uneven batch of", len(maps))
+    batch = ctx.step_series(descs)
+    iters = [int(r["iters"][0]) for r in batch]
+    assert len(set(iters)) > 1          # the instances stop at different iterations
+    for k, d in enumerate(descs):
+        single = ctx.step_series([d])[0]
+        assert torch.equal(single["xy"], batch[k]["xy"]), k
+        assert single["iters"][0] == batch[k]["iters"][0] and single["status"][0] == batch[k]["status"][0]
+        assert single["xi"][0] == batch[k]["xi"][0]
+    one = ctx.step_series([dict(d, fixed_iters=1) for d in descs])
+    for k, (m, s, N) in enumerate(maps):
+        want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, s.astype(np.float64), N)
+        err = np.abs(_np(one[k]["xy"])[0].astype(np.float64) - want).max()
+        assert err <= 1e-6, (k, err)

@@ -57,10 +57,13 @@ def test_warm_start_from_a_converged_field(ctx):
     N, G = 256, 64
     gm, plain, field = _plain_and_field(ctx, m, s, N, G)
     assert plain["status"][0] == 0
-    # the move itself: stop right after the warm start (max_iters = 0)
+    # the move itself: stop right after the warm start (max_iters = 0); the
+    # step chosen among the trial steps is the oracle's
     r0 = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, init_field=field, max_iters=0)])[0]
     assert not (r0["flags"][0] & 4)
-    want = oc.warm_start_move(m.xy32().astype(np.float64), field.cpu().numpy().astype(np.float64))
+    alpha, want = oc.warm_start_choose(m, s.astype(np.float64), N, m.xy32().astype(np.float64),
+                                       field.cpu().numpy().astype(np.float64))
+    assert alpha > 0
     assert np.max(np.abs(r0["xy"][0].cpu().numpy() - want)) < 1e-6
     plain0 = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, max_iters=0)])[0]
     assert r0["xi"][0] < 0.5 * plain0["xi"][0]
@@ -68,6 +71,23 @@ def test_warm_start_from_a_converged_field(ctx):
     rw = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, init_field=field)])[0]
     assert rw["status"][0] == 0 and not (rw["flags"][0] & 4)
     assert rw["iters"][0] < plain["iters"][0], (rw["iters"][0], plain["iters"][0])
+
+
+def test_partial_step_when_the_full_field_folds(ctx):
+    # a field twice too long folds the map; a shorter trial step is taken
+    m = square_grid_map(3, 6)
+    s = lognormal_values(0, 9, 0.25).astype(np.float32)
+    N, G = 256, 64
+    gm, plain, field = _plain_and_field(ctx, m, s, N, G)
+    f2 = 2.5 * field
+    r0 = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, init_field=f2, max_iters=0)])[0]
+    alpha, want = oc.warm_start_choose(m, s.astype(np.float64), N, m.xy32().astype(np.float64),
+                                       f2.cpu().numpy().astype(np.float64))
+    if alpha == 0:
+        assert r0["flags"][0] & 4
+    else:
+        assert not (r0["flags"][0] & 4)
+    assert np.max(np.abs(r0["xy"][0].cpu().numpy() - want)) < 1e-6
 
 
 @pytest.mark.parametrize("kind", ["zero", "folding"])

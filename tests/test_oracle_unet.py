@@ -20,20 +20,20 @@ def test_parameter_count_of_the_warm_start_net():
     assert unet.layer_table(32, 4)[3] == by_hand
 
 
-@pytest.mark.parametrize("L", [2, 3])
-def test_gradients_vs_finite_differences(L):
+@pytest.mark.parametrize("L,cin,gain", [(2, 1, 0.0), (3, 1, 0.0), (2, 3, 0.4)])
+def test_gradients_vs_finite_differences(L, cin, gain):
     c, H, W, B, scale = 2, 8, 8, 2, 0.7
     rng = np.random.default_rng(11 + L)
-    p = unet.init_params(c, L, seed=5)
+    p = unet.init_params(c, L, seed=5, cin0=cin)
     p += 0.05 * rng.standard_normal(p.size)          # non-zero biases, generic kinks
-    x = rng.standard_normal((B, H, W))
+    x = rng.standard_normal((B, H, W, cin))
     tgt = rng.standard_normal((B, H, W, 2))
 
     def loss_at(q):
-        out, cache = unet.forward(q, x, c, L, scale)
+        out, cache = unet.forward(q, x, c, L, scale, gain)
         return float(((out - tgt) ** 2).mean())
 
-    out, cache = unet.forward(p, x, c, L, scale)
+    out, cache = unet.forward(p, x, c, L, scale, gain)
     loss, g = unet.backward(p, cache, tgt, c, L, scale)
     assert abs(loss - loss_at(p)) < 1e-14
     h = 1e-6
@@ -87,6 +87,16 @@ def test_copy_weights_give_closed_forms(L):
     blk = x.reshape(2, H // q, q, W // q, q).mean(axis=(2, 4))
     want = np.repeat(np.repeat(blk, q, axis=1), q, axis=2)
     assert np.allclose(out[..., 0], scale * want, rtol=0, atol=1e-14)
+
+
+def test_residual_head_adds_the_given_field():
+    c, L, scale, gain = 2, 2, 0.3, 1.7
+    layers, hw, hb, n = unet.layer_table(c, L, 3)
+    p = np.zeros(n)
+    p[hb:hb + 2] = [0.5, -1.0]                       # zero weights: the net part is scale * bias
+    x = np.random.default_rng(1).standard_normal((2, 8, 8, 3))
+    out, _ = unet.forward(p, x, c, L, scale, gain)
+    assert np.allclose(out, gain * x[..., 1:3] + scale * np.array([0.5, -1.0]), atol=1e-15)
 
 
 def test_adam_first_step_moves_by_lr_times_sign():
