@@ -47,7 +47,22 @@ struct IterState {
   int32_t pad1;
 };
 
-struct Inst {
+// Pointer policies of the instance descriptor: the host fills generic
+// pointers; kernels view the same bits as global-address-space pointers so
+// that their loads, stores and atomics compile to global (not flat)
+// instructions, which do not stall on LDS traffic.
+#define CG_GLOBAL __attribute__((address_space(1)))
+#define CG_CONST __attribute__((address_space(4)))
+template <typename T> using g_ptr = T CG_GLOBAL*;
+struct PlainPtr {
+  template <typename T> using p = T*;
+};
+struct GlobalPtr {
+  template <typename T> using p = T CG_GLOBAL*;
+};
+
+template <typename PP>
+struct InstT {
   int32_t N, R, n_vert, n_pts;        // n_pts = vertices + tracer points
   int32_t n_edges, n_rings, n_lut, pad0;
   int32_t tw, th, ntx, nty;           // integral-image tiling
@@ -55,35 +70,39 @@ struct Inst {
   float shape, tol;
   int64_t pitch, xing_cap;
   // topology
-  const int4* edges;                  // (v0, v1, region A, region B)
-  const int32_t* ring_off;
-  const int32_t* ring_idx;
-  const int32_t* reg_ring_off;        // [R+1] region -> rings
-  const int32_t* reg_rings;
+  typename PP::template p<const int4> edges;                  // (v0, v1, region A, region B)
+  typename PP::template p<const int32_t> ring_off;
+  typename PP::template p<const int32_t> ring_idx;
+  typename PP::template p<const int32_t> reg_ring_off;        // [R+1] region -> rings
+  typename PP::template p<const int32_t> reg_rings;
   // state and buffers
-  float2* xy;                         // [n_vert] vertex positions (iterated in place)
-  float2* extra;                      // [n_pts - n_vert] tracer points moved along
-  const float2* src_xy;               // starting positions copied in by k_init (or null)
-  const float2* src_extra;
-  const float* init_field;            // warm-start displacement [2][G+1][G+1] or null
+  typename PP::template p<float2> xy;                         // [n_vert] vertex positions (iterated in place)
+  typename PP::template p<float2> extra;                      // [n_pts - n_vert] tracer points moved along
+  typename PP::template p<const float2> src_xy;               // starting positions copied in by k_init (or null)
+  typename PP::template p<const float2> src_extra;
+  typename PP::template p<const float> init_field;            // warm-start displacement [G][G][2] at pixel centres, or null
   int64_t init_G;
-  const float* values;                // [R]
-  uint32_t* row_cnt;                  // [N]
-  uint32_t* row_off;                  // [N+1]
-  uint64_t* xing;                     // [xing_cap]
-  uint16_t* labels;                   // [N][N]
-  int64_t* counts;                    // [R+1]
-  float* lut;                         // [n_lut]
-  const float* density;               // dense texture (replaces labels + lut) or null
-  void* S;
-  void* T;
-  void* HA;
-  void* HB;
-  void* agg;                          // integral-image tile aggregates
-  void* carry;                        // integral-image carries
-  double* areas;                      // [R+1]
-  IterState* st;
+  typename PP::template p<const float> values;                // [R]
+  typename PP::template p<uint32_t> row_cnt;                  // [N]
+  typename PP::template p<uint32_t> row_off;                  // [N+1]
+  typename PP::template p<uint64_t> xing;                     // [xing_cap]
+  typename PP::template p<uint16_t> labels;                   // [N][N]
+  typename PP::template p<int64_t> counts;                    // [R+1]
+  typename PP::template p<float> lut;                         // [n_lut]
+  typename PP::template p<const float> density;               // dense texture (replaces labels + lut) or null
+  typename PP::template p<void> S;
+  typename PP::template p<void> T;
+  typename PP::template p<void> HA;
+  typename PP::template p<void> HB;
+  typename PP::template p<void> agg;                          // integral-image tile aggregates
+  typename PP::template p<void> carry;                        // integral-image carries
+  typename PP::template p<double> areas;                      // [R+1]
+  typename PP::template p<IterState> st;
 };
+
+using Inst = InstT<PlainPtr>;
+using InstG = InstT<GlobalPtr>;
+static_assert(sizeof(Inst) == sizeof(InstG), "descriptor views share one layout");
 
 // Per-kind block offsets over the instances of a batch ([n+1] each).
 struct Batch {
@@ -111,7 +130,38 @@ __device__ __forceinline__ int find_inst(const int64_t* off, int n, int64_t b) {
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
-__device__ __forceinline__ bool inst_done(const Batch& B, const Inst& I) {
+// Descriptor k of a batch in registers (scalar loads; read-only in kernels).
+__device__ __forceinline__ InstG inst_of(const Batch& B, int k) {
+  return __builtin_bit_cast(InstG, ((const Inst CG_CONST*)B.inst)[k]);
+}
+
+// Loads and stores of HIP vector types through global-space pointers.
+__device__ __forceinline__ int4 ld4(g_ptr<const int4> p) {
+  typedef int v4 __attribute__((ext_vector_type(4)));
+  const v4 v = *(g_ptr<const v4>)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld2(g_ptr<const float2> p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(g_ptr<const v2>)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(g_ptr<float2> p, float2 a) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  *(g_ptr<v2>)p = v2{a.x, a.y};
+}
+
+// Global-space atomics (relaxed, device scope).
+template <typename T>
+__device__ __forceinline__ T g_atomic_add(g_ptr<T> p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_atomic_or(g_ptr<T> p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool inst_done(const Batch& B, const InstG& I) {
   return B.skip_done && I.st != nullptr && I.st->done != 0;
 }
 

@@ -36,7 +36,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // (the map is invariant to a common scale of the density).
 __global__ __launch_bounds__(256) void k_density(Batch B) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void t_uniform(F x, F y, F q1x, F q1y, F q2x, F q2y, 
 
 // Steps 5 at one node: D = t(.; d) - t(.; d0) (eqs.(2)-(3)).
 template <typename F>
-__device__ __forceinline__ void node_disp(const F* S, const F* T, const F* HA, const F* HB, int64_t pitch,
+__device__ __forceinline__ void node_disp(g_ptr<const F> S, g_ptr<const F> T, g_ptr<const F> HA, g_ptr<const F> HB, int64_t pitch,
                                           int N, F C, int i, int j, F& dx, F& dy) {
   const F invN = F(1) / F(N);
   const F x = F(i) * invN, y = F(j) * invN;
@@ -129,12 +129,12 @@ __device__ __forceinline__ void node_disp(const F* S, const F* T, const F* HA, c
 template <typename F>
 __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
-  float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
-  const float2 p = *ptr;
+  g_ptr<float2> ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
+  const float2 p = ld2(ptr);
   const int N = I.N;
   const F fN = F(N);
   const F u = fmin(fmax(F(p.x) * fN, F(0)), fN);
@@ -142,10 +142,10 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   const int i0 = min((int)floor(u), N - 1);
   const int j0 = min((int)floor(v), N - 1);
   const F fx = u - F(i0), fy = v - F(j0);
-  const F* S = (const F*)I.S;
-  const F* T = (const F*)I.T;
-  const F* HA = (const F*)I.HA;
-  const F* HB = (const F*)I.HB;
+  g_ptr<const F> S = (g_ptr<const F>)I.S;
+  g_ptr<const F> T = (g_ptr<const F>)I.T;
+  g_ptr<const F> HA = (g_ptr<const F>)I.HA;
+  g_ptr<const F> HB = (g_ptr<const F>)I.HB;
   const int64_t pitch = I.pitch;
   const F C = S[(int64_t)N * pitch + N];
   F d00x, d00y, d10x, d10y, d01x, d01y, d11x, d11y;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   float2 o;
   o.x = (float)fmin(fmax(F(p.x) + dx, F(0)), F(1));
   o.y = (float)fmin(fmax(F(p.y) + dy, F(0)), F(1));
-  *ptr = o;
+  st2(ptr, o);
 }
 
 // Warm start: move every point by alpha times a displacement field given
@@ -169,46 +169,47 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
 // chosen step (IterState::ws_alpha; 0 = no move).
 __global__ __launch_bounds__(256) void k_apply_field(Batch B, float alpha) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   const float a = alpha < 0.f ? I.st->ws_alpha : alpha;
   if (a == 0.f) return;
-  float2* ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
-  const float2 p = *ptr;
+  g_ptr<float2> ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
+  const float2 p = ld2(ptr);
   const int G = (int)I.init_G;
-  const float2* F = (const float2*)I.init_field;
+  g_ptr<const float2> F = (g_ptr<const float2>)I.init_field;
   float dx, dy;
   if (G == 1) {
-    dx = F[0].x;
-    dy = F[0].y;
+    const float2 f0 = ld2(F);
+    dx = f0.x;
+    dy = f0.y;
   } else {
     const float u = fminf(fmaxf(p.x * G - 0.5f, 0.f), (float)(G - 1));
     const float v = fminf(fmaxf(p.y * G - 0.5f, 0.f), (float)(G - 1));
     const int i0 = min((int)floorf(u), G - 2), j0 = min((int)floorf(v), G - 2);
     const float fx = u - i0, fy = v - j0;
-    const float2 a = F[(int64_t)j0 * G + i0], b = F[(int64_t)j0 * G + i0 + 1];
-    const float2 c = F[(int64_t)(j0 + 1) * G + i0], d = F[(int64_t)(j0 + 1) * G + i0 + 1];
+    const float2 a = ld2(F + (int64_t)j0 * G + i0), b = ld2(F + (int64_t)j0 * G + i0 + 1);
+    const float2 c = ld2(F + (int64_t)(j0 + 1) * G + i0), d = ld2(F + (int64_t)(j0 + 1) * G + i0 + 1);
     const float w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
     dx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
     dy = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
   }
-  *ptr = make_float2(fminf(fmaxf(p.x + a * dx, 0.f), 1.f), fminf(fmaxf(p.y + a * dy, 0.f), 1.f));
+  st2(ptr, make_float2(fminf(fmaxf(p.x + a * dx, 0.f), 1.f), fminf(fmaxf(p.y + a * dy, 0.f), 1.f)));
 }
 
 // Warm start: put the starting positions back (before the next trial step).
 __global__ __launch_bounds__(256) void k_restore(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   if (idx < I.n_vert) {
-    if (I.src_xy && I.src_xy != I.xy) I.xy[idx] = I.src_xy[idx];
+    if (I.src_xy && I.src_xy != I.xy) st2(I.xy + idx, ld2(I.src_xy + idx));
   } else {
     const int64_t e = idx - I.n_vert;
-    if (I.src_extra && I.src_extra != I.extra) I.extra[e] = I.src_extra[e];
+    if (I.src_extra && I.src_extra != I.extra) st2(I.extra + e, ld2(I.src_extra + e));
   }
 }
 
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void k_tracer_field(int G, const float2* fin, 
 // Shoelace area of every region (sum over its rings), FP64, fixed order.
 __global__ __launch_bounds__(256) void k_areas(Batch B) {
   const int k = find_inst(B.off_regions, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int v = 1 + (int)(blockIdx.x - B.off_regions[k]);
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
     const int r = I.reg_rings[rr];
     const int beg = I.ring_off[r], len = I.ring_off[r + 1] - beg;
     for (int e = t; e < len; e += 256) {
-      const float2 a = I.xy[I.ring_idx[beg + e]];
-      const float2 b = I.xy[I.ring_idx[beg + (e + 1 == len ? 0 : e + 1)]];
+      const float2 a = ld2(I.xy + I.ring_idx[beg + e]);
+      const float2 b = ld2(I.xy + I.ring_idx[beg + (e + 1 == len ? 0 : e + 1)]);
       acc += (double)a.x * (double)b.y - (double)b.x * (double)a.y;
     }
   }
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
 // CG_FLAG_FALLBACK when no trial step beat the plain start.
 __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   se = block_sum(se, red);
   me = block_max(me, red);
   if (t != 0) return;
-  IterState* st = I.st;
+  g_ptr<IterState> st = I.st;
   const double xi = me, eps = R > 0 ? se / R : 0.0;
   I.areas[0] = 1.0 - sa;
   st->xi = xi;
@@ -379,12 +380,15 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
 // Reset the iteration state and copy the starting positions.
 __global__ __launch_bounds__(256) void k_init(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
   if (idx == 0) {
     IterState z = {};
     z.best_xi = 1e300;
-    *I.st = z;
+    static_assert(sizeof(IterState) % 4 == 0, "state is copied as 32-bit words");
+    const uint32_t* src = (const uint32_t*)&z;
+    g_ptr<uint32_t> dst = (g_ptr<uint32_t>)I.st;
+    for (int w = 0; w < (int)(sizeof(IterState) / 4); ++w) dst[w] = src[w];
   }
   // the row counters are accumulated with atomics and cleared by their
   // consumers; scratch memory starts with arbitrary contents
@@ -394,10 +398,10 @@ __global__ __launch_bounds__(256) void k_init(Batch B) {
   }
   if (idx >= I.n_pts) return;
   if (idx < I.n_vert) {
-    if (I.src_xy && I.src_xy != I.xy) I.xy[idx] = I.src_xy[idx];
+    if (I.src_xy && I.src_xy != I.xy) st2(I.xy + idx, ld2(I.src_xy + idx));
   } else {
     const int64_t e = idx - I.n_vert;
-    if (I.src_extra && I.src_extra != I.extra) I.extra[e] = I.src_extra[e];
+    if (I.src_extra && I.src_extra != I.extra) st2(I.extra + e, ld2(I.src_extra + e));
   }
 }
 

@@ -35,21 +35,21 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
 
 __global__ __launch_bounds__(256) void k_raster_count(Batch B) {
   const int k = find_inst(B.off_edges, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
-  const int4 E = I.edges[e];
+  const int4 E = ld4(I.edges + e);
   const float scale = (float)(kSub * I.N);
-  const int ya = snapc(I.xy[E.x].y, scale), yb = snapc(I.xy[E.y].y, scale);
+  const int ya = snapc(ld2(I.xy + E.x).y, scale), yb = snapc(ld2(I.xy + E.y).y, scale);
   int q0, q1;
   crossed_rows(ya, yb, I.N, q0, q1);
-  for (int q = q0; q < q1; ++q) atomicAdd(&I.row_cnt[q], 1u);
+  for (int q = q0; q < q1; ++q) g_atomic_add(&I.row_cnt[q], 1u);
 }
 
 __global__ __launch_bounds__(1024) void k_raster_scan(Batch B) {
   const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ uint32_t wsum[16];
   const int N = I.N, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -89,21 +89,21 @@ __global__ __launch_bounds__(1024) void k_raster_scan(Batch B) {
     I.row_off[N] = total;
     I.st->xings = total;
     I.st->contested = 0;
-    if ((int64_t)total > I.xing_cap) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+    if ((int64_t)total > I.xing_cap) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
   }
   for (int v = t; v <= I.R; v += 1024) I.counts[v] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   const int k = find_inst(B.off_edges, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
-  const int4 E = I.edges[e];
+  const int4 E = ld4(I.edges + e);
   const int N = I.N;
   const float scale = (float)(kSub * N);
-  const float2 pa = I.xy[E.x], pb = I.xy[E.y];
+  const float2 pa = ld2(I.xy + E.x), pb = ld2(I.xy + E.y);
   int ax = snapc(pa.x, scale), ay = snapc(pa.y, scale);
   int bx = snapc(pb.x, scale), by = snapc(pb.y, scale);
   int q0, q1;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
     const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
     int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
     if (p0 > N) p0 = N;
-    const uint32_t slot = I.row_off[q] + atomicAdd(&I.row_cnt[q], 1u);
+    const uint32_t slot = I.row_off[q] + g_atomic_add(&I.row_cnt[q], 1u);
     if ((int64_t)slot < I.xing_cap) I.xing[slot] = (uint64_t)p0 | regs;
   }
 }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void claims_label(const Claims& c, int& lab, int& n) 
 // serial walk instead (folded maps, coincident crossings).
 __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   const int k = find_inst(B.off_rows, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   constexpr int RPW = kFillRows / 4;   // rows per wavefront
   __shared__ uint64_t xs[4][kFillXing];
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
         const uint32_t en = lane + 1 == (int)cnt ? (uint32_t)N : pnext;
         if (en > p0) {
           if (lds_counts) atomicAdd(&lcount[label], en - p0);
-          else atomicAdd((unsigned long long*)&I.counts[label], (unsigned long long)(en - p0));
+          else g_atomic_add((g_ptr<unsigned long long>)&I.counts[label], (unsigned long long)(en - p0));
           if (nclaim > 1) cont = en - p0;
         }
       }
@@ -355,16 +355,16 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
         const uint32_t first = cnt ? (uint32_t)(srt[w][0] & 0xFFFFu) : (uint32_t)N;
         if (first > 0) {
           if (lds_counts) atomicAdd(&lcount[0], first);
-          else atomicAdd((unsigned long long*)&I.counts[0], (unsigned long long)first);
+          else g_atomic_add((g_ptr<unsigned long long>)&I.counts[0], (unsigned long long)first);
         }
       }
       for (int d = 32; d >= 1; d >>= 1) cont += __shfl_xor(cont, d, 64);
       if (lane == 0) {
         if (cont) {
           atomicAdd(&contested_blk, cont);
-          atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+          g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_CONTESTED);
         }
-        if (bad) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+        if (bad) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
       }
       ngroups = __popcll(lastmask);
     } else if (lane == 0) {
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
           if (n > 1) cont += len;
           if (len) {
             if (lds_counts) atomicAdd(&lcount[lab], len);
-            else atomicAdd((unsigned long long*)&I.counts[lab], (unsigned long long)len);
+            else g_atomic_add((g_ptr<unsigned long long>)&I.counts[lab], (unsigned long long)len);
           }
           prev = p0;
         }
@@ -406,14 +406,14 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       ngroups = nsp - 1;
       if (cont) {
         atomicAdd(&contested_blk, cont);
-        atomicOr(&I.st->flags, CG_FLAG_CONTESTED);
+        g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_CONTESTED);
       }
-      if (bad || over) atomicOr(&I.st->flags, CG_FLAG_OVERFLOW);
+      if (bad || over) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
     }
       ngroups = __shfl(ngroups, 0, 64);
       // fill: spans 0..ngroups, the last span with start <= p holds pixel p
       const int nsp = (int)ngroups + 1;
-      uint16_t* row = I.labels + (int64_t)q * N;
+      g_ptr<uint16_t> row = I.labels + (int64_t)q * N;
       for (int p = lane * 8; p < N; p += 64 * 8) {
         int lo = 0, hi = nsp;
         while (hi - lo > 1) {
@@ -448,8 +448,8 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   // the block's counts into the instance totals (integer sums: order-independent)
   if (lds_counts)
     for (int v = t; v <= R; v += 256)
-      if (lcount[v]) atomicAdd((unsigned long long*)&I.counts[v], (unsigned long long)lcount[v]);
-  if (t == 0 && contested_blk) atomicAdd((unsigned long long*)&I.st->contested, contested_blk);
+      if (lcount[v]) g_atomic_add((g_ptr<unsigned long long>)&I.counts[v], (unsigned long long)lcount[v]);
+  if (t == 0 && contested_blk) g_atomic_add((g_ptr<unsigned long long>)&I.st->contested, (unsigned long long)contested_blk);
 }
 
 void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,

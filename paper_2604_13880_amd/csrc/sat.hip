@@ -33,7 +33,7 @@ namespace cgk {
 // power of two >= 16, so every 8-wide chunk is entirely inside or outside;
 // each chunk is one 16-byte (labels) or two 16-byte (density) loads.
 template <bool DENSE, int TH, int W, int NT>
-__device__ __forceinline__ void stage_density(const Inst& I, const float* lut_s, bool lut_lds, int xs,
+__device__ __forceinline__ void stage_density(const InstG& I, const float* lut_s, bool lut_lds, int xs,
                                               int y0, float (*ds)[W]) {
   constexpr int CH = W / 8;
   const int N = I.N;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   constexpr int NW = TW / 64, D = TW + TH - 1, SB = kSub_Rows, E = TW / 64;
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
     }
   }
   __syncthreads();
-  Cy* agg = (Cy*)I.agg;
+  g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   const int64_t tid = (int64_t)ty * L.ntx + tx;
   for (int r = t; r < TH; r += TW) agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rsum[r]);
   A tot, tA0, tA1, tB0, tB1, z;
@@ -244,11 +244,11 @@ template <int P, int TW, int TH>
 __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
   typedef typename PT<P>::carry Cy;
   const int k = find_inst(B.off_carry1, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int64_t idx = (int64_t)(blockIdx.x - B.off_carry1[k]) * 256 + threadIdx.x;
-  Cy* agg = (Cy*)I.agg;
+  g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   if (idx < L.NY) {
     const int q = (int)idx;
     Cy run = 0;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
 // Mass of tile row ty on the anti-diagonal side u (tiles fully below u give
 // their totals through the tile-row prefix, at most two tiles are cut).
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_a(const Cy* agg, const SatLayout& L, int ty, int64_t u) {
+__device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t u) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(u - y0 - TW - TH + 2, TW);
@@ -287,7 +287,7 @@ __device__ __forceinline__ Cy band_a(const Cy* agg, const SatLayout& L, int ty, 
 }
 
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_b(const Cy* agg, const SatLayout& L, int ty, int64_t v) {
+__device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t v) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(v + y0 - TW + 1, TW);
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
   const int k = find_inst(B.off_carry2, B.n, blockIdx.x);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ Cy part[256];
   __shared__ Cy partC[256];
@@ -319,8 +319,8 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   const int CH = L.carry_ch, IPB = 256 / CH;
   const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
   const int64_t idx = (int64_t)(blockIdx.x - B.off_carry2[k]) * IPB + j;
-  const Cy* agg = (const Cy*)I.agg;
-  Cy* carry = (Cy*)I.carry;
+  g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
+  g_ptr<Cy> carry = (g_ptr<Cy>)I.carry;
   const int64_t nS = L.NX + 1;
   const int seg = idx < nS ? 0 : (idx < nS + L.LA ? 1 : (idx < nS + L.LA + L.LB ? 2 : 3));
   const int ty0 = ch * kCarryRows;
@@ -338,9 +338,9 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
         v = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx] +
             agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + (i - tx * TW)];
       } else if (seg == 1) {
-        v = band_a<TW, TH>(agg, L, ty, idx - nS - 1);
+        v = band_a<TW, TH, Cy>(agg, L, ty, idx - nS - 1);
       } else if (seg == 2) {
-        v = band_b<TW, TH>(agg, L, ty, idx - nS - L.LA - L.NY);
+        v = band_b<TW, TH, Cy>(agg, L, ty, idx - nS - L.LA - L.NY);
         w = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx];
       }
     }
@@ -373,11 +373,11 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
     if (seg == 1) {
       const int64_t a = idx - nS;
       carry[L.TAc + (int64_t)nty * L.LA + a] = run;
-      if (a <= 2 * N) ((St*)I.HA)[a] = (St)run;                 // HA(s) = TA(s-1, N), s = a
+      if (a <= 2 * N) ((g_ptr<St>)I.HA)[a] = (St)run;                 // HA(s) = TA(s-1, N), s = a
     } else if (seg == 2) {
       const int64_t bi = idx - nS - L.LA, v = bi - L.NY;
       carry[L.TBc + (int64_t)nty * L.LB + bi] = run;
-      if (v >= -N && v <= N) ((St*)I.HB)[N - v] = (St)(C - run);  // HB(r) = C - TB(-r, N)
+      if (v >= -N && v <= N) ((g_ptr<St>)I.HB)[N - v] = (St)(C - run);  // HB(r) = C - TB(-r, N)
     }
   }
 }
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
-  const Inst I = B.inst[k];  // register copy: stores below cannot alias it
+  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ float ds[SB][XW];
   __shared__ A Ms[SB][XW];
@@ -408,8 +408,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
-  const Cy* agg = (const Cy*)I.agg;
-  const Cy* carry = (const Cy*)I.carry;
+  g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
+  g_ptr<const Cy> carry = (g_ptr<const Cy>)I.carry;
   // carries entering the tile
   A sacc, saccN;
   from_carry(sacc, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
@@ -431,8 +431,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   for (int r = t; r < TH; r += TW) from_carry(rc_s[r], agg[L.RC + (int64_t)tx * L.NY + y0 + r]);
   if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  St* S = (St*)I.S;
-  St* T = (St*)I.T;
+  g_ptr<St> S = (g_ptr<St>)I.S;
+  g_ptr<St> T = (g_ptr<St>)I.T;
   const int64_t pitch = I.pitch;
   const int i = x0 + t;
   if (ty == 0) {
