@@ -321,6 +321,18 @@ void shape_for(const cg_ctx* c, int N, int prec, int64_t batch_px, int* tw, int*
   *th = it->second.second;
 }
 
+// Tiles never wider than the narrowest texture of a launch (64 at least):
+// then every tile column lies inside the table's pitch, and the integral-
+// image writer stores whole tile rows without a per-column bound check
+// (columns past N land in the row padding).
+void cap_shape(int minN, int* tw, int* th) {
+  const int cap = std::max(64, minN);
+  if (*tw <= cap) return;
+  *tw = cap;
+  if (cap == 64) *th = 16;
+  else if (*th > 32) *th = 32;
+}
+
 struct HookCtx {
   cg_ctx* c;
   int it;
@@ -531,6 +543,7 @@ int cg_integral_image(cg_ctx* c, int N, const uint16_t* labels, const float* lut
   hipStream_t st = pick_stream(c, stream);
   int tw, th;
   shape_for(c, N, precision, (int64_t)N * N, &tw, &th);
+  cap_shape(N, &tw, &th);
   Spec s;
   s.N = N;
   s.labels = (uint16_t*)labels;
@@ -685,7 +698,7 @@ int cg_autotune(cg_ctx* c, int N, int precision, int32_t batch, const char* cach
   int btw = 0, bth = 0;
   for (auto& sh : kShapes) {
     const int tw = sh[0], th = sh[1];
-    if (th > 2 * N && tw > N) continue;
+    if (tw > std::max(64, N)) continue;
     std::vector<Spec> specs(batch);
     for (auto& sp : specs) {
       sp.N = N;
@@ -790,6 +803,7 @@ int cg_tile_shape(const cg_ctx* c, int N, int precision, int64_t batch_pixels, i
   if (!c || !tw || !th || !pow2_ok(N)) return CG_EINVAL;
   int a, b;
   shape_for(c, N, precision, batch_pixels, &a, &b);
+  cap_shape(N, &a, &b);
   *tw = a;
   *th = b;
   return CG_OK;
@@ -817,6 +831,9 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
   }
   int tw, th;
   shape_for(c, maxN, prec, px, &tw, &th);
+  int minN = maxN;
+  for (auto& s : specs) minN = std::min(minN, s.N);
+  cap_shape(minN, &tw, &th);
   Needs nd;
   nd.raster = nd.sat = nd.areas = true;
   Plan P;

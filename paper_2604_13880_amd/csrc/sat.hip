@@ -148,6 +148,20 @@ __device__ __forceinline__ A block_exclusive_scan(A v, A* wt, A& total) {
   return pre;
 }
 
+// Local sums inside a tile (at most one tile row-strip of mass) use float
+// in the float-stored modes and double in the double mode; the long sums
+// (carries across tiles, row carries) use the mode's accumulator.
+template <int P> struct LocalT { typedef float type; };
+template <> struct LocalT<CG_F64> { typedef double type; };
+
+__device__ __forceinline__ float lc_shfl_up(float v, int d) { return __shfl_up(v, d, 64); }
+__device__ __forceinline__ double lc_shfl_up(double v, int d) { return __shfl_up(v, d, 64); }
+
+template <typename A, typename Lc>
+__device__ __forceinline__ void acc_add_local(A& a, Lc x) { acc_add(a, x); }
+template <>
+__device__ __forceinline__ void acc_add_local<double, double>(double& a, double x) { a += x; }
+
 // Tile aggregates from line sums of the raw densities (no row scans):
 // column totals, row totals, and the sums h_a(s) over the tile's
 // anti-diagonals s = (p - x0) + (q - y0) and h_b(s) over its diagonals
@@ -177,8 +191,8 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
   if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  A col, ha0, ha1, hb0, hb1;
-  acc_zero(col); acc_zero(ha0); acc_zero(ha1); acc_zero(hb0); acc_zero(hb1);
+  typedef typename LocalT<P>::type Lc;
+  Lc col = 0, ha0 = 0, ha1 = 0, hb0 = 0, hb1 = 0;
   const int c1 = t + TW;
   const bool has1 = c1 < D;
   for (int r0 = 0; r0 < TH; r0 += SB) {
@@ -186,25 +200,25 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
     stage_density<DENSE, SB, TW, TW>(I, lut_s, lut_lds, x0, y0 + r0, ds);
     __syncthreads();
     for (int rr = w; rr < SB; rr += NW) {   // row totals, one wavefront per row
-      A v;
-      acc_zero(v);
+      Lc v = 0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) acc_add(v, ds[rr][lane + 64 * e]);
-      v = wave_sum(v);
-      if (lane == 0) rsum[r0 + rr] = v;
+      for (int e = 0; e < E; ++e) v += (Lc)ds[rr][lane + 64 * e];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+      if (lane == 0) acc_zero(rsum[r0 + rr]), acc_add_local(rsum[r0 + rr], v);
     }
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr;
-      acc_add(col, ds[rr][t]);
+      col += (Lc)ds[rr][t];
       const int ca = t - r;                 // anti-diagonal slot t meets row r here
-      if (ca >= 0) acc_add(ha0, ds[rr][ca]);
+      if (ca >= 0) ha0 += (Lc)ds[rr][ca];
       const int cb = t + r - TH + 1;        // diagonal slot t
-      if (cb >= 0) acc_add(hb0, ds[rr][cb]);
+      if (cb >= 0) hb0 += (Lc)ds[rr][cb];
       if (has1) {                           // slots t + TW (always right of column 0)
         const int ca1 = c1 - r, cb1 = c1 + r - TH + 1;
-        if (ca1 < TW) acc_add(ha1, ds[rr][ca1]);
-        if (cb1 < TW) acc_add(hb1, ds[rr][cb1]);
+        if (ca1 < TW) ha1 += (Lc)ds[rr][ca1];
+        if (cb1 < TW) hb1 += (Lc)ds[rr][cb1];
       }
     }
   }
@@ -212,29 +226,34 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   const int64_t tid = (int64_t)ty * L.ntx + tx;
   for (int r = t; r < TH; r += TW) agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rsum[r]);
-  A tot, tA0, tA1, tB0, tB1, z;
+  A tot, tA0, tA1, tB0, tB1, z, colA, ha0A, ha1A, hb0A, hb1A;
   acc_zero(z);
-  A ex = block_exclusive_scan<A, NW>(col, wt, tot);
-  acc_addv(ex, col);
+  acc_zero(colA); acc_add_local(colA, col);
+  acc_zero(ha0A); acc_add_local(ha0A, ha0);
+  acc_zero(ha1A); acc_add_local(ha1A, ha1);
+  acc_zero(hb0A); acc_add_local(hb0A, hb0);
+  acc_zero(hb1A); acc_add_local(hb1A, hb1);
+  A ex = block_exclusive_scan<A, NW>(colA, wt, tot);
+  acc_addv(ex, colA);
   agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(ex);
   if (t == 0) {
     agg[L.colsum + tid * (TW + 1)] = (Cy)0;
     agg[L.tileTot + tid] = to_carry(tot);
   }
-  A ea0 = block_exclusive_scan<A, NW>(ha0, wt, tA0);
-  A ea1 = block_exclusive_scan<A, NW>(has1 ? ha1 : z, wt, tA1);
-  A eb0 = block_exclusive_scan<A, NW>(hb0, wt, tB0);
-  A eb1 = block_exclusive_scan<A, NW>(has1 ? hb1 : z, wt, tB1);
-  acc_addv(ea0, acc_half(ha0));
-  acc_addv(eb0, acc_half(hb0));
+  A ea0 = block_exclusive_scan<A, NW>(ha0A, wt, tA0);
+  A ea1 = block_exclusive_scan<A, NW>(has1 ? ha1A : z, wt, tA1);
+  A eb0 = block_exclusive_scan<A, NW>(hb0A, wt, tB0);
+  A eb1 = block_exclusive_scan<A, NW>(has1 ? hb1A : z, wt, tB1);
+  acc_addv(ea0, acc_half(ha0A));
+  acc_addv(eb0, acc_half(hb0A));
   agg[L.cdfA + tid * D + t] = to_carry(ea0);
   agg[L.cdfB + tid * D + t] = to_carry(eb0);
   if (has1) {
     A a1 = tA0, b1 = tB0;
     acc_addv(a1, ea1);
-    acc_addv(a1, acc_half(ha1));
+    acc_addv(a1, acc_half(ha1A));
     acc_addv(b1, eb1);
-    acc_addv(b1, acc_half(hb1));
+    acc_addv(b1, acc_half(hb1A));
     agg[L.cdfA + tid * D + c1] = to_carry(a1);
     agg[L.cdfB + tid * D + c1] = to_carry(b1);
   }
@@ -382,104 +401,162 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   }
 }
 
+// Writer pass.  Per tile (TW threads, one per node column, TH rows, halo
+// of TH columns on both sides for the tilted areas):
+//   S(i, j) = Stop(i) + sum_{rows < j} rc(q) + sum_{rows < j} Rloc(i, q)
+//   TA(s, j) = TAc(s) + sum_{rows < j} rc(q) + la(s, j)   (likewise TB)
+//   T = TA - TB = (TAc - TBc) + (la - lb)   (the row-carry sums cancel)
+// where rc(q) is the row integral left of the tile, Rloc/Mloc the row
+// integral from the tile's left edge (to the node / to the pixel centre)
+// and la, lb the running sums of Mloc along each anti-diagonal / diagonal
+// slot.  Rloc, Mloc, la, lb stay within one tile and are kept in the
+// local type; Stop, TAc, TBc and the row-carry sum in the accumulator.
 template <int P, int TW, int TH, bool DENSE>
 __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
+  typedef typename LocalT<P>::type Lc;
   constexpr int NW = TW / 64, SB = kSub_Rows;
   constexpr int XW = TW + 2 * TH;          // columns x0-TH .. x0+TW+TH-1
   constexpr int NSL = TW + TH + 1;         // anti-diagonal / diagonal slots
+  constexpr int E = XW / 64 + 1;           // strip columns per lane in the row scans
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ float ds[SB][XW];
-  __shared__ A Ms[SB][XW];
-  __shared__ A taB[SB][NSL];
-  __shared__ A tbB[SB][NSL];
+  __shared__ Lc Ml[SB][XW];                // Mloc of the sub-band's rows
+  __shared__ Lc la_s[SB][NSL];
+  __shared__ Lc lb_s[SB][NSL];
+  __shared__ A ca_s[NSL];                  // TAc - TBc pairs are formed from these
+  __shared__ A cb_s[NSL];
   __shared__ A rc_s[TH];
-  __shared__ float lut_s[kLutLds];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int N = I.N;
   const SatLayout L = sat_layout(N, TW, TH);
   const int tile = (int)(b - B.off_tiles[k]);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
-  const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
+  const bool lut_lds = false;        // LUT read through the cache: more blocks fit in LDS
+  const float* lut_s = nullptr;
   g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
   g_ptr<const Cy> carry = (g_ptr<const Cy>)I.carry;
   // carries entering the tile
-  A sacc, saccN;
-  from_carry(sacc, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
+  A stop, stopN;
+  from_carry(stop, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
   const bool extra = (x0 + TW == N) && t == 0;   // the tile column that ends at node column N
-  if (extra) from_carry(saccN, carry[L.Stop + (int64_t)ty * (L.NX + 1) + N]);
-  else acc_zero(saccN);
-  A ra[2], rb[2];
-  const int s1 = t + TW;
-  const bool has1 = s1 < NSL;
-  from_carry(ra[0], carry[L.TAc + (int64_t)ty * L.LA + x0 + y0 + t]);
-  from_carry(rb[0], carry[L.TBc + (int64_t)ty * L.LB + (x0 - y0 - TH + L.NY) + t]);
-  if (has1) {
-    from_carry(ra[1], carry[L.TAc + (int64_t)ty * L.LA + x0 + y0 + s1]);
-    from_carry(rb[1], carry[L.TBc + (int64_t)ty * L.LB + (x0 - y0 - TH + L.NY) + s1]);
-  } else {
-    acc_zero(ra[1]);
-    acc_zero(rb[1]);
+  if (extra) from_carry(stopN, carry[L.Stop + (int64_t)ty * (L.NX + 1) + N]);
+  else acc_zero(stopN);
+  for (int sl = t; sl < NSL; sl += TW) {
+    from_carry(ca_s[sl], carry[L.TAc + (int64_t)ty * L.LA + x0 + y0 + sl]);
+    from_carry(cb_s[sl], carry[L.TBc + (int64_t)ty * L.LB + (x0 - y0 - TH + L.NY) + sl]);
   }
   for (int r = t; r < TH; r += TW) from_carry(rc_s[r], agg[L.RC + (int64_t)tx * L.NY + y0 + r]);
-  if (lut_lds)
-    for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
   g_ptr<St> S = (g_ptr<St>)I.S;
   g_ptr<St> T = (g_ptr<St>)I.T;
   const int64_t pitch = I.pitch;
   const int i = x0 + t;
+  // tiles are never wider than max(64, N) and the pitch holds every tile
+  // column: columns past N are row padding, written without a bound check
   if (ty == 0) {
-    if (i <= N) {
-      S[i] = (St)0;
-      T[i] = (St)0;
-    }
+    S[i] = (St)0;
+    T[i] = (St)0;
     if (extra) {
       S[N] = (St)0;
       T[N] = (St)0;
     }
   }
+  const int s1 = t + TW;
+  const bool has1 = s1 < NSL;
+  A bsum;                  // sum of the row carries of the rows done
+  acc_zero(bsum);
+  Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0;
   for (int r0 = 0; r0 < TH; r0 += SB) {
     __syncthreads();
     stage_density<DENSE, SB, XW, TW>(I, lut_s, lut_lds, x0 - TH, y0 + r0, ds);
     __syncthreads();
-    // centre prefix over the tile and its halo, exact at the tile's left edge
-    sub_band_scan<A, XW, NW>(ds, Ms, rc_s + r0, TH, (A*)nullptr);
-    __syncthreads();
-    for (int rr = 0; rr < SB; ++rr) {
-      const int r = r0 + rr, j = y0 + r + 1;
-      A v = Ms[rr][t + TH];                  // R(x0+t) = M - d/2
-      acc_add(v, -0.5f * ds[rr][t + TH]);
-      acc_addv(sacc, v);
-      if (extra) acc_addv(saccN, Ms[rr][TW + TH]);   // column N lies outside: R = M there
-      if (j <= N) {
-        if (i <= N) S[(int64_t)j * pitch + i] = to_store(sacc);
-        if (extra) S[(int64_t)j * pitch + N] = to_store(saccN);
+    // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, one
+    // wavefront per row, lanes holding E consecutive columns
+    for (int rr = w; rr < SB; rr += NW) {
+      Lc dv[E], loc = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int c = lane * E + e;
+        dv[e] = c < XW ? (Lc)ds[rr][c] : (Lc)0;
+        loc += dv[e];
       }
-      acc_addv(ra[0], Ms[rr][t + TH - 1 - r]);   // anti-diagonal slot t meets row y0+r here
-      acc_addv(rb[0], Ms[rr][t + r]);            // diagonal slot t
-      taB[rr][t] = ra[0];
-      tbB[rr][t] = rb[0];
-      if (has1) {
-        acc_addv(ra[1], Ms[rr][s1 + TH - 1 - r]);
-        acc_addv(rb[1], Ms[rr][s1 + r]);
-        taB[rr][s1] = ra[1];
-        tbB[rr][s1] = rb[1];
+      Lc x = loc;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const Lc y = lc_shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      Lc run = x - loc;                    // exclusive prefix of the lane
+      Lc lv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        lv[e] = run;
+        run += dv[e];
+      }
+      const Lc l0 = __shfl(lv[TH % E], TH / E, 64);   // prefix at strip column TH
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int c = lane * E + e;
+        if (c < XW) Ml[rr][c] = (lv[e] - l0) + (Lc)0.5 * dv[e];
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < SB; ++rr) {
+      const int r = r0 + rr, j = y0 + r + 1;
+      acc_addv(bsum, rc_s[r]);
+      rsum += Ml[rr][t + TH] - (Lc)0.5 * (Lc)ds[rr][t + TH];   // Rloc at node column i
+      if (extra) rsumN += Ml[rr][TW + TH];                     // column N lies outside: d = 0
+      if (j <= N) {
+        {
+          A v = stop;
+          acc_addv(v, bsum);
+          acc_add_local(v, rsum);
+          S[(int64_t)j * pitch + i] = to_store(v);
+        }
+        if (extra) {
+          A v = stopN;
+          acc_addv(v, bsum);
+          acc_add_local(v, rsumN);
+          S[(int64_t)j * pitch + N] = to_store(v);
+        }
+      }
+      la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
+      lb0 += Ml[rr][t + r];                // diagonal slot t
+      la_s[rr][t] = la0;
+      lb_s[rr][t] = lb0;
+      if (has1) {
+        la1 += Ml[rr][s1 + TH - 1 - r];
+        lb1 += Ml[rr][s1 + r];
+        la_s[rr][s1] = la1;
+        lb_s[rr][s1] = lb1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;
       if (j > N) break;
       const int64_t row = (int64_t)j * pitch;
-      if (i <= N) T[row + i] = to_store(acc_sub(taB[rr][t + r + 1], tbB[rr][t + TH - 1 - r]));
-      if (extra) T[row + N] = to_store(acc_sub(taB[rr][TW + r + 1], tbB[rr][TW + TH - 1 - r]));
+      {
+        const int sa = t + r + 1, sb = t + TH - 1 - r;
+        A v = acc_sub(ca_s[sa], cb_s[sb]);
+        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+        T[row + i] = to_store(v);
+      }
+      if (extra) {
+        const int sa = TW + r + 1, sb = TW + TH - 1 - r;
+        A v = acc_sub(ca_s[sa], cb_s[sb]);
+        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+        T[row + N] = to_store(v);
+      }
     }
   }
 }
