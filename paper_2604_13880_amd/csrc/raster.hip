@@ -434,12 +434,13 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
             v[c] = sp_lab[w][s2];
           }
         }
-        uint4 pk;
+        typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+        u32x4_t pk;
         pk.x = v[0] | ((uint32_t)v[1] << 16);
         pk.y = v[2] | ((uint32_t)v[3] << 16);
         pk.z = v[4] | ((uint32_t)v[5] << 16);
         pk.w = v[6] | ((uint32_t)v[7] << 16);
-        *(uint4*)(row + p) = pk;     // N is a multiple of 8
+        *(g_ptr<u32x4_t>)(row + p) = pk;     // N is a multiple of 8
       }
       if (lane == 0) I.row_cnt[q] = 0u;
     }

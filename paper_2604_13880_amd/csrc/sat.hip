@@ -28,43 +28,72 @@
 
 namespace cgk {
 
-// Stage the densities of rows [y0, y0+TH) x columns [xs, xs+W) into LDS
-// (zero outside the texture).  W and xs are multiples of 8 and N is a
-// power of two >= 16, so every 8-wide chunk is entirely inside or outside;
-// each chunk is one 16-byte (labels) or two 16-byte (density) loads.
-template <bool DENSE, int TH, int W, int NT>
-__device__ __forceinline__ void stage_density(const InstG& I, const float* lut_s, bool lut_lds, int xs,
-                                              int y0, float (*ds)[W]) {
-  constexpr int CH = W / 8;
-  const int N = I.N;
-  for (int c = threadIdx.x; c < TH * CH; c += NT) {
-    const int r = c / CH, k = c - r * CH;
-    const int q = y0 + r, p = xs + 8 * k;
-    float v[8];
-    if (q < N && p >= 0 && p < N) {
-      const int64_t at = (int64_t)q * N + p;
-      if (DENSE) {
-        const float4 a = *(const float4*)(I.density + at);
-        const float4 b = *(const float4*)(I.density + at + 4);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-      } else {
-        const uint4 L = *(const uint4*)(I.labels + at);
-        const uint32_t w4[4] = {L.x, L.y, L.z, L.w};
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Staging of the densities of rows [y0, y0+SBR) x columns [xs, xs+W) into
+// LDS (zero outside the texture), split into a load (global -> registers)
+// and a store (registers -> LUT -> LDS) so that the next sub-band's loads
+// are in flight while the current one is processed.  W and xs are
+// multiples of 8 and N is a power of two >= 16, so every 8-wide chunk is
+// entirely inside or outside; a chunk is one 16-byte (labels) or two
+// 16-byte (density) loads.
+template <bool DENSE, int SBR, int W, int NT>
+struct Stager {
+  static constexpr int CH = W / 8;
+  static constexpr int NC = (SBR * CH + NT - 1) / NT;   // chunks per thread
+  u32x4_t lab[NC];
+  f32x4_t da[DENSE ? NC : 1], db[DENSE ? NC : 1];
+  bool ok[NC];
+
+  __device__ __forceinline__ void load(const InstG& I, int xs, int y0) {
+    const int N = I.N;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int lab = (int)((w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-          v[e] = lab < I.n_lut ? (lut_lds ? lut_s[lab] : I.lut[lab]) : 0.f;  // labels outside the LUT carry no mass
+    for (int n = 0; n < NC; ++n) {
+      const int c = threadIdx.x + n * NT;
+      const int r = c / CH, k = c - r * CH;
+      const int q = y0 + r, p = xs + 8 * k;
+      ok[n] = c < SBR * CH && q < N && p >= 0 && p < N;
+      if (ok[n]) {
+        const int64_t at = (int64_t)q * N + p;
+        if (DENSE) {
+          da[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at);
+          db[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at + 4);
+        } else {
+          lab[n] = *(g_ptr<const u32x4_t>)(I.labels + at);
         }
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.f;
     }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) ds[r][8 * k + e] = v[e];
   }
-}
+
+  __device__ __forceinline__ void store(const InstG& I, const float* lut_s, bool lut_lds, float (*ds)[W]) const {
+#pragma unroll
+    for (int n = 0; n < NC; ++n) {
+      const int c = threadIdx.x + n * NT;
+      if (c >= SBR * CH) break;
+      const int r = c / CH, k = c - r * CH;
+      float v[8];
+      if (!ok[n]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 0.f;
+      } else if (DENSE) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[e] = da[DENSE ? n : 0][e];
+          v[4 + e] = db[DENSE ? n : 0][e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int lb = (int)((lab[n][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          v[e] = lb < I.n_lut ? (lut_lds ? lut_s[lb] : I.lut[lb]) : 0.f;  // labels outside the LUT carry no mass
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ds[r][8 * k + e] = v[e];
+    }
+  }
+};
 
 constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of the tile)
 
@@ -195,9 +224,12 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   Lc col = 0, ha0 = 0, ha1 = 0, hb0 = 0, hb1 = 0;
   const int c1 = t + TW;
   const bool has1 = c1 < D;
+  Stager<DENSE, SB, TW, TW> stg;
+  stg.load(I, x0, y0);
   for (int r0 = 0; r0 < TH; r0 += SB) {
     __syncthreads();
-    stage_density<DENSE, SB, TW, TW>(I, lut_s, lut_lds, x0, y0 + r0, ds);
+    stg.store(I, lut_s, lut_lds, ds);
+    if (r0 + SB < TH) stg.load(I, x0, y0 + r0 + SB);   // next sub-band in flight
     __syncthreads();
     for (int rr = w; rr < SB; rr += NW) {   // row totals, one wavefront per row
       Lc v = 0;
@@ -473,9 +505,12 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   A bsum;                  // sum of the row carries of the rows done
   acc_zero(bsum);
   Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0;
+  Stager<DENSE, SB, XW, TW> stg;
+  stg.load(I, x0 - TH, y0);
   for (int r0 = 0; r0 < TH; r0 += SB) {
     __syncthreads();
-    stage_density<DENSE, SB, XW, TW>(I, lut_s, lut_lds, x0 - TH, y0 + r0, ds);
+    stg.store(I, lut_s, lut_lds, ds);
+    if (r0 + SB < TH) stg.load(I, x0 - TH, y0 + r0 + SB);   // next sub-band in flight
     __syncthreads();
     // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, one
     // wavefront per row, lanes holding E consecutive columns
