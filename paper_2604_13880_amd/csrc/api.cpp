@@ -27,11 +27,11 @@
 namespace cgk {
 void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u);
-bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, int64_t tiles, int64_t c1,
+bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, bool il, int64_t tiles, int64_t c1,
                 int64_t c2, hipStream_t s, StageHook h, void* u);
 bool sat_shape_supported(int tw, int th);
 void launch_density(const Batch& B, hipStream_t s);
-void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s);
+void launch_map(const Batch& B, int prec, bool il, int64_t pt_blocks, hipStream_t s);
 void launch_apply_field(const Batch& B, int64_t pt_blocks, float alpha, hipStream_t s);
 void launch_restore(const Batch& B, int64_t pt_blocks, hipStream_t s);
 void launch_log_density(const uint16_t* labels, const int64_t* counts, const float* values, int R, int N, float shape,
@@ -113,6 +113,7 @@ struct Plan {
   Batch B{};
   int prec = CG_F32, tw = 128, th = 16;
   bool dense = false;
+  bool il = false;          // S and T interleaved as (S, T) pairs (the plan owns both tables)
   int n = 0;
   int64_t edge_blocks = 0, row_blocks = 0, tiles = 0, c1 = 0, c2 = 0, pt_blocks = 0, reg_blocks = 0;
   IterState* d_state = nullptr;
@@ -130,6 +131,8 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   P.th = th;
   P.dense = dense;
   P.inst.assign(n, Inst{});
+  P.il = nd.sat && !dense;
+  for (const Spec& s : specs) P.il = P.il && !s.S && !s.T;
   // scratch layout
   struct Own {
     int64_t rowcnt = -1, rowoff = -1, xing = -1, labels = -1, counts = -1, lut = -1, S = -1, T = -1,
@@ -197,8 +200,12 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     if (!dense && !s.lut) ow.lut = take(sizeof(float) * (R + 1));
     if (nd.sat) {
       const size_t tb = store_size(prec) * (size_t)(N + 1) * I.pitch;
-      if (!s.S) ow.S = take(tb);
-      if (!s.T) ow.T = take(tb);
+      if (P.il) {
+        ow.S = take(2 * tb);    // (S, T) pairs; T is the second element
+      } else {
+        if (!s.S) ow.S = take(tb);
+        if (!s.T) ow.T = take(tb);
+      }
       if (!s.HA) ow.HA = take(store_size(prec) * (2 * N + 1));
       if (!s.HB) ow.HB = take(store_size(prec) * (2 * N + 1));
       ow.agg = take(carry_size(prec) * L.agg_elems);
@@ -231,6 +238,7 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     if (ow.lut >= 0) I.lut = (float*)at(ow.lut);
     if (ow.S >= 0) I.S = at(ow.S);
     if (ow.T >= 0) I.T = at(ow.T);
+    if (P.il) I.T = at(ow.S) + store_size(prec);
     if (ow.HA >= 0) I.HA = at(ow.HA);
     if (ow.HB >= 0) I.HB = at(ow.HB);
     I.agg = at(ow.agg);
@@ -354,9 +362,9 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   hk(cgk::ST_DENSITY, 0);
   cgk::launch_density(P.B, st);
   hk(cgk::ST_DENSITY, 1);
-  cgk::launch_sat(P.B, P.prec, P.tw, P.th, false, P.tiles, P.c1, P.c2, st, h, u);
+  cgk::launch_sat(P.B, P.prec, P.tw, P.th, false, P.il, P.tiles, P.c1, P.c2, st, h, u);
   hk(cgk::ST_MAP, 0);
-  cgk::launch_map(P.B, P.prec, P.pt_blocks, st);
+  cgk::launch_map(P.B, P.prec, P.il, P.pt_blocks, st);
   hk(cgk::ST_MAP, 1);
   hk(cgk::ST_AREAS, 0);
   cgk::launch_areas(P.B, P.reg_blocks, st);
@@ -561,7 +569,7 @@ int cg_integral_image(cg_ctx* c, int N, const uint16_t* labels, const float* lut
   int rc = build_plan(c, {s}, precision, tw, th, density != nullptr, nd, st, P, "call");
   if (rc) return rc;
   P.B.skip_done = 0;
-  if (!cgk::launch_sat(P.B, precision, tw, th, density != nullptr, P.tiles, P.c1, P.c2, st, nullptr, nullptr))
+  if (!cgk::launch_sat(P.B, precision, tw, th, density != nullptr, P.il, P.tiles, P.c1, P.c2, st, nullptr, nullptr))
     return fail(c, CG_EUNSUPPORTED, "cg_integral_image: unsupported tile shape");
   out->N = N;
   out->precision = precision;
@@ -601,7 +609,7 @@ int cg_map_points(cg_ctx* c, const cg_inim* im, const float* xy_in, float* xy_ou
   if (rc) return rc;
   P.B.skip_done = 0;
   cgk::launch_init(P.B, P.pt_blocks, st);
-  cgk::launch_map(P.B, im->precision, P.pt_blocks, st);
+  cgk::launch_map(P.B, im->precision, P.il, P.pt_blocks, st);
   return check_launch(c);
 }
 
@@ -711,10 +719,10 @@ int cg_autotune(cg_ctx* c, int N, int precision, int32_t batch, const char* cach
     Plan P;
     if ((rc = build_plan(c, specs, precision, tw, th, false, nd, st, P, "tune"))) break;
     P.B.skip_done = 0;
-    for (int w = 0; w < 2; ++w) cgk::launch_sat(P.B, precision, tw, th, false, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
+    for (int w = 0; w < 2; ++w) cgk::launch_sat(P.B, precision, tw, th, false, P.il, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
     const int reps = 5;
     hipEventRecord(e0, st);
-    for (int r = 0; r < reps; ++r) cgk::launch_sat(P.B, precision, tw, th, false, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
+    for (int r = 0; r < reps; ++r) cgk::launch_sat(P.B, precision, tw, th, false, P.il, P.tiles, P.c1, P.c2, st, nullptr, nullptr);
     hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(c, CG_EDEVICE, "cg_autotune: device error"); break; }
     float ms = 0.f;

@@ -101,15 +101,17 @@ __device__ __forceinline__ void t_uniform(F x, F y, F q1x, F q1y, F q2x, F q2y, 
 }
 
 // Steps 5 at one node: D = t(.; d) - t(.; d0) (eqs.(2)-(3)).
-template <typename F>
+// Table element (i, j) of S or T lives at [(j * pitch + i) * ST] (ST = 2 for
+// interleaved (S, T) pairs, 1 for separate tables).
+template <typename F, int ST>
 __device__ __forceinline__ void node_disp(g_ptr<const F> S, g_ptr<const F> T, g_ptr<const F> HA, g_ptr<const F> HB, int64_t pitch,
                                           int N, F C, int i, int j, F& dx, F& dy) {
   const F invN = F(1) / F(N);
   const F x = F(i) * invN, y = F(j) * invN;
-  const F s = S[(int64_t)j * pitch + i];
-  const F siN = S[(int64_t)N * pitch + i];
-  const F sNj = S[(int64_t)j * pitch + N];
-  const F tt = T[(int64_t)j * pitch + i];
+  const F s = S[((int64_t)j * pitch + i) * ST];
+  const F siN = S[((int64_t)N * pitch + i) * ST];
+  const F sNj = S[((int64_t)j * pitch + N) * ST];
+  const F tt = T[((int64_t)j * pitch + i) * ST];
   const F ha = HA[i + j];
   const F hb = HB[j - i + N];
   const F a = s, b = siN - s, dl = sNj - s, g = C - siN - sNj + s;
@@ -126,7 +128,7 @@ __device__ __forceinline__ void node_disp(g_ptr<const F> S, g_ptr<const F> T, g_
 }
 
 // Step 6: bilinear interpolation of D at each point, clamp to [0,1]^2.
-template <typename F>
+template <typename F, int ST>
 __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
@@ -147,12 +149,12 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   g_ptr<const F> HA = (g_ptr<const F>)I.HA;
   g_ptr<const F> HB = (g_ptr<const F>)I.HB;
   const int64_t pitch = I.pitch;
-  const F C = S[(int64_t)N * pitch + N];
+  const F C = S[((int64_t)N * pitch + N) * ST];
   F d00x, d00y, d10x, d10y, d01x, d01y, d11x, d11y;
-  node_disp(S, T, HA, HB, pitch, N, C, i0, j0, d00x, d00y);
-  node_disp(S, T, HA, HB, pitch, N, C, i0 + 1, j0, d10x, d10y);
-  node_disp(S, T, HA, HB, pitch, N, C, i0, j0 + 1, d01x, d01y);
-  node_disp(S, T, HA, HB, pitch, N, C, i0 + 1, j0 + 1, d11x, d11y);
+  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0, j0, d00x, d00y);
+  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0 + 1, j0, d10x, d10y);
+  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0, j0 + 1, d01x, d01y);
+  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0 + 1, j0 + 1, d11x, d11y);
   const F w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
   const F dx = w00 * d00x + w10 * d10x + w01 * d01x + w11 * d11x;
   const F dy = w00 * d00y + w10 * d10y + w01 * d01y + w11 * d11y;
@@ -432,10 +434,15 @@ __global__ __launch_bounds__(256) void k_frames(const float2* a, const float2* b
 void launch_density(const Batch& B, hipStream_t s) {
   hipLaunchKernelGGL(k_density, dim3(B.n), dim3(256), 0, s, B);
 }
-void launch_map(const Batch& B, int prec, int64_t pt_blocks, hipStream_t s) {
+void launch_map(const Batch& B, int prec, bool il, int64_t pt_blocks, hipStream_t s) {
   if (pt_blocks <= 0) return;
-  if (prec == CG_F64) hipLaunchKernelGGL(k_map_points<double>, dim3(pt_blocks), dim3(256), 0, s, B);
-  else hipLaunchKernelGGL(k_map_points<float>, dim3(pt_blocks), dim3(256), 0, s, B);
+  if (prec == CG_F64) {
+    if (il) hipLaunchKernelGGL((k_map_points<double, 2>), dim3(pt_blocks), dim3(256), 0, s, B);
+    else hipLaunchKernelGGL((k_map_points<double, 1>), dim3(pt_blocks), dim3(256), 0, s, B);
+  } else {
+    if (il) hipLaunchKernelGGL((k_map_points<float, 2>), dim3(pt_blocks), dim3(256), 0, s, B);
+    else hipLaunchKernelGGL((k_map_points<float, 1>), dim3(pt_blocks), dim3(256), 0, s, B);
+  }
 }
 void launch_apply_field(const Batch& B, int64_t pt_blocks, float alpha, hipStream_t s) {
   if (pt_blocks > 0) hipLaunchKernelGGL(k_apply_field, dim3(pt_blocks), dim3(256), 0, s, B, alpha);

@@ -443,7 +443,14 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
 // and la, lb the running sums of Mloc along each anti-diagonal / diagonal
 // slot.  Rloc, Mloc, la, lb stay within one tile and are kept in the
 // local type; Stop, TAc, TBc and the row-carry sum in the accumulator.
-template <int P, int TW, int TH, bool DENSE>
+template <typename St> struct Pair;
+template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// IL: S and T interleaved in one table of (S, T) pairs (the series driver's
+// own buffers: one store per node, and the mapping kernel gathers both
+// values of a node from one cache line); else two separate tables.
+template <int P, int TW, int TH, bool DENSE, bool IL>
 __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
@@ -486,20 +493,28 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     from_carry(cb_s[sl], carry[L.TBc + (int64_t)ty * L.LB + (x0 - y0 - TH + L.NY) + sl]);
   }
   for (int r = t; r < TH; r += TW) from_carry(rc_s[r], agg[L.RC + (int64_t)tx * L.NY + y0 + r]);
+  typedef typename Pair<St>::type St2;
   g_ptr<St> S = (g_ptr<St>)I.S;
   g_ptr<St> T = (g_ptr<St>)I.T;
+  g_ptr<St2> ST = (g_ptr<St2>)I.S;
   const int64_t pitch = I.pitch;
   const int i = x0 + t;
   // tiles are never wider than max(64, N) and the pitch holds every tile
   // column: columns past N are row padding, written without a bound check
   if (ty == 0) {
-    S[i] = (St)0;
-    T[i] = (St)0;
-    if (extra) {
-      S[N] = (St)0;
-      T[N] = (St)0;
+    if (IL) {
+      ST[i] = St2{(St)0, (St)0};
+      if (extra) ST[N] = St2{(St)0, (St)0};
+    } else {
+      S[i] = (St)0;
+      T[i] = (St)0;
+      if (extra) {
+        S[N] = (St)0;
+        T[N] = (St)0;
+      }
     }
   }
+  St sv[SB], svN[SB];      // S of the sub-band's rows, stored with T (interleaved tables)
   const int s1 = t + TW;
   const bool has1 = s1 < NSL;
   A bsum;                  // sum of the row carries of the rows done
@@ -554,13 +569,15 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
           A v = stop;
           acc_addv(v, bsum);
           acc_add_local(v, rsum);
-          S[(int64_t)j * pitch + i] = to_store(v);
+          sv[rr] = (St)to_store(v);
+          if (!IL) S[(int64_t)j * pitch + i] = sv[rr];
         }
         if (extra) {
           A v = stopN;
           acc_addv(v, bsum);
           acc_add_local(v, rsumN);
-          S[(int64_t)j * pitch + N] = to_store(v);
+          svN[rr] = (St)to_store(v);
+          if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
         }
       }
       la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
@@ -584,13 +601,15 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
         const int sa = t + r + 1, sb = t + TH - 1 - r;
         A v = acc_sub(ca_s[sa], cb_s[sb]);
         acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        T[row + i] = to_store(v);
+        if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
+        else T[row + i] = to_store(v);
       }
       if (extra) {
         const int sa = TW + r + 1, sb = TW + TH - 1 - r;
         A v = acc_sub(ca_s[sa], cb_s[sb]);
         acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        T[row + N] = to_store(v);
+        if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
+        else T[row + N] = to_store(v);
       }
     }
   }
@@ -599,7 +618,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
 // host launchers --------------------------------------------------------------
 
 template <int P, int TW, int TH>
-static void launch_sat_t(const Batch& B, bool dense, int64_t tiles, int64_t c1, int64_t c2,
+static void launch_sat_t(const Batch& B, bool dense, bool il, int64_t tiles, int64_t c1, int64_t c2,
                          hipStream_t s, StageHook h, void* u) {
   auto hk = [&](int st, int after) { if (h) h(st, after, u); };
   hk(ST_SAT_REDUCE, 0);
@@ -613,29 +632,30 @@ static void launch_sat_t(const Batch& B, bool dense, int64_t tiles, int64_t c1, 
   hipLaunchKernelGGL((k_sat_carry2<P, TW, TH>), dim3(c2), dim3(256), 0, s, B);
   hk(ST_SAT_CARRY2, 1);
   hk(ST_SAT_FINAL, 0);
-  if (dense) hipLaunchKernelGGL((k_sat_final<P, TW, TH, true>), dim3(tiles), dim3(TW), 0, s, B);
-  else hipLaunchKernelGGL((k_sat_final<P, TW, TH, false>), dim3(tiles), dim3(TW), 0, s, B);
+  if (dense) hipLaunchKernelGGL((k_sat_final<P, TW, TH, true, false>), dim3(tiles), dim3(TW), 0, s, B);
+  else if (il) hipLaunchKernelGGL((k_sat_final<P, TW, TH, false, true>), dim3(tiles), dim3(TW), 0, s, B);
+  else hipLaunchKernelGGL((k_sat_final<P, TW, TH, false, false>), dim3(tiles), dim3(TW), 0, s, B);
   hk(ST_SAT_FINAL, 1);
 }
 
 template <int P>
-static bool launch_sat_p(const Batch& B, int tw, int th, bool dense, int64_t tiles, int64_t c1,
+static bool launch_sat_p(const Batch& B, int tw, int th, bool dense, bool il, int64_t tiles, int64_t c1,
                          int64_t c2, hipStream_t s, StageHook h, void* u) {
-  if (tw == 64 && th == 16) launch_sat_t<P, 64, 16>(B, dense, tiles, c1, c2, s, h, u);
-  else if (tw == 128 && th == 16) launch_sat_t<P, 128, 16>(B, dense, tiles, c1, c2, s, h, u);
-  else if (tw == 128 && th == 32) launch_sat_t<P, 128, 32>(B, dense, tiles, c1, c2, s, h, u);
-  else if (tw == 256 && th == 32) launch_sat_t<P, 256, 32>(B, dense, tiles, c1, c2, s, h, u);
-  else if (tw == 256 && th == 64) launch_sat_t<P, 256, 64>(B, dense, tiles, c1, c2, s, h, u);
+  if (tw == 64 && th == 16) launch_sat_t<P, 64, 16>(B, dense, il, tiles, c1, c2, s, h, u);
+  else if (tw == 128 && th == 16) launch_sat_t<P, 128, 16>(B, dense, il, tiles, c1, c2, s, h, u);
+  else if (tw == 128 && th == 32) launch_sat_t<P, 128, 32>(B, dense, il, tiles, c1, c2, s, h, u);
+  else if (tw == 256 && th == 32) launch_sat_t<P, 256, 32>(B, dense, il, tiles, c1, c2, s, h, u);
+  else if (tw == 256 && th == 64) launch_sat_t<P, 256, 64>(B, dense, il, tiles, c1, c2, s, h, u);
   else return false;
   return true;
 }
 
-bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, int64_t tiles, int64_t c1,
+bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, bool il, int64_t tiles, int64_t c1,
                 int64_t c2, hipStream_t s, StageHook h, void* u) {
-  if (prec == CG_F32) return launch_sat_p<CG_F32>(B, tw, th, dense, tiles, c1, c2, s, h, u);
-  if (prec == CG_COMP) return launch_sat_p<CG_COMP>(B, tw, th, dense, tiles, c1, c2, s, h, u);
-  if (prec == CG_F64) return launch_sat_p<CG_F64>(B, tw, th, dense, tiles, c1, c2, s, h, u);
-  if (prec == CG_F64ACC) return launch_sat_p<CG_F64ACC>(B, tw, th, dense, tiles, c1, c2, s, h, u);
+  if (prec == CG_F32) return launch_sat_p<CG_F32>(B, tw, th, dense, il, tiles, c1, c2, s, h, u);
+  if (prec == CG_COMP) return launch_sat_p<CG_COMP>(B, tw, th, dense, il, tiles, c1, c2, s, h, u);
+  if (prec == CG_F64) return launch_sat_p<CG_F64>(B, tw, th, dense, il, tiles, c1, c2, s, h, u);
+  if (prec == CG_F64ACC) return launch_sat_p<CG_F64ACC>(B, tw, th, dense, il, tiles, c1, c2, s, h, u);
   return false;
 }
 
