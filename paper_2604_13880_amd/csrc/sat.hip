@@ -183,8 +183,31 @@ __device__ __forceinline__ A block_exclusive_scan(A v, A* wt, A& total) {
 template <int P> struct LocalT { typedef float type; };
 template <> struct LocalT<CG_F64> { typedef double type; };
 
-__device__ __forceinline__ float lc_shfl_up(float v, int d) { return __shfl_up(v, d, 64); }
-__device__ __forceinline__ double lc_shfl_up(double v, int d) { return __shfl_up(v, d, 64); }
+// Inclusive scan over a wavefront with DPP row shifts and row broadcasts
+// (no LDS traffic): within each row of 16 lanes by shifts of 1, 2, 4, 8,
+// then row 0's total into row 1, row 2's into row 3, and lane 31's into
+// rows 2 and 3.  Lanes whose source lies outside the row read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_take(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename Lc>
+__device__ __forceinline__ Lc wave_inclusive_scan_dpp(Lc x) {
+  x += dpp_take<0x111, 0xf>(x);   // row_shr:1
+  x += dpp_take<0x112, 0xf>(x);   // row_shr:2
+  x += dpp_take<0x114, 0xf>(x);   // row_shr:4
+  x += dpp_take<0x118, 0xf>(x);   // row_shr:8
+  x += dpp_take<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_take<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
 
 template <typename A, typename Lc>
 __device__ __forceinline__ void acc_add_local(A& a, Lc x) { acc_add(a, x); }
@@ -537,12 +560,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
         dv[e] = c < XW ? (Lc)ds[rr][c] : (Lc)0;
         loc += dv[e];
       }
-      Lc x = loc;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const Lc y = lc_shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
+      const Lc x = wave_inclusive_scan_dpp(loc);
       Lc run = x - loc;                    // exclusive prefix of the lane
       Lc lv[E];
 #pragma unroll
