@@ -39,15 +39,15 @@ METRIC = "ms to 1% area error per cartogram; Mpx-iter/s; learned+batched vs plai
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    "config2": dict(seed=2000, R=100, n=50000, fractal=True, sigma=1.5, N=1024, precision=1,
+    "fractal100_1024": dict(seed=2000, R=100, n=50000, fractal=True, sigma=1.5, N=1024, precision=1,
                     desc="100 fractal Voronoi regions (~50k vertices), lognormal sigma 1.5, 1024^2 texture, "
                          "iterate to max area error < 1% or the stopping rule, compensated FP32 integral images"),
-    "config1": dict(seed=1000, R=32, n=2000, fractal=False, sigma=1.0, N=256, precision=1, fixed=20,
+    "voronoi32_256": dict(seed=1000, R=32, n=2000, fractal=False, sigma=1.0, N=256, precision=1, fixed=20,
                     desc="32 Voronoi regions (~2k vertices), lognormal sigma 1, 256^2 texture, 20 iterations"),
-    "config3": dict(seed=3000, R=200, n=200000, fractal=True, sigma=1.0, N=2048, precision=3, T=64,
+    "series64_fractal200_2048": dict(seed=3000, R=200, n=200000, fractal=True, sigma=1.0, N=2048, precision=3, T=64,
                     desc="200 fractal Voronoi regions (~200k vertices), 2048^2, 64 time steps of a geometric "
                          "random walk (step sigma 0.1), all steps batched (direct), FP64-accumulated integral images"),
-    "config4": dict(seed=4000, count=256, precision=1,
+    "uneven256_256to2048": dict(seed=4000, count=256, precision=1,
                     desc="256 independent fractal Voronoi cartograms, textures 256^2-2048^2, 16-300 regions, "
                          "lognormal sigma 0.5-2, ~500 R N/1024 vertices each, one launch per kernel per iteration "
                          "for all instances, compensated FP32 integral images, each to its own stopping rule"),
@@ -61,12 +61,12 @@ def _uneven_map(spec):
 
 
 def run_uneven(a, B, ctx, torch):
-    """Config 4: an uneven batch of independent cartograms in one series call."""
+    """An uneven batch of independent cartograms in one series call."""
     import multiprocessing as mp
     from synth import uneven_batch_specs
-    w = WORKLOADS["config4"]
+    w = WORKLOADS["uneven256_256to2048"]
     specs = uneven_batch_specs(w["seed"], w["count"])
-    log("config4: generating", len(specs), "maps")
+    log("uneven256_256to2048: generating", len(specs), "maps")
     with mp.get_context("fork").Pool(16) as pool:
         maps = pool.map(_uneven_map, specs, chunksize=4)
     gms = [ctx.map_from(m) for m, s in maps]
@@ -104,7 +104,7 @@ def run_uneven(a, B, ctx, torch):
         per /= max(int(iters.max()), 1)
         ach = per / (stage_ms / stage_n * 1e-3) / 1e9
         roof = dict(bound="hbm", kernel=a.stage, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=counter_traffic(a.stage, "config4"),
+                    frac=ach / HBM_PEAK_GBS, traffic=counter_traffic(a.stage, "uneven256_256to2048"),
                     avg_launch_us=stage_ms / stage_n * 1e3, launches=stage_n, alg_bytes_per_launch=per,
                     note="bytes per launch = mean over the run's iterations of the instances still running")
     return dict(workload=w["desc"], instances=len(specs), texture_mpx=px / 1e6, ms_batch=ms,
@@ -176,7 +176,7 @@ def roofline(stage, ms, n, N, prec, n_pts, instances, workload):
 
 
 def run_learned(a, B, ctx, torch):
-    """Config 5: warm start by the trained net followed by the plain
+    """Warm start by the trained net followed by the plain
     iteration, against the plain method, on held-out seeded maps."""
     from paper_2604_13880_amd import learned as Lr
     path = os.path.join(ROOT, "paper_2604_13880_amd", "weights", "warm_start_512.bin")
@@ -184,7 +184,7 @@ def run_learned(a, B, ctx, torch):
         return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
     net = B.Net(ctx, max_batch=8, **Lr.NET_CFG)
     net.load(path)
-    log("config5: generating", a.learned_maps, "held-out maps")
+    log("learned_512: generating", a.learned_maps, "held-out maps")
     maps = Lr.make_maps(range(Lr.TEST_SEED0, Lr.TEST_SEED0 + a.learned_maps), workers=16)
     rep = Lr.compare(ctx, net, maps, single=min(16, a.learned_maps), area_source=1)
     rep["workload"] = ("held-out seeded maps, 50-150 fractal Voronoi regions (~250 vertices per region), "
@@ -255,9 +255,9 @@ def precision_table(ctx, B, m, values, N):
 
 
 def run_series(a, w, B, ctx, torch):
-    """Config 3: every step of a 64-step value series as one direct batch."""
+    """Every step of a 64-step value series as one direct batch."""
     from synth import random_walk_series, voronoi_map
-    log("config3: generating map")
+    log("series64_fractal200_2048: generating map")
     m = voronoi_map(w["seed"], w["R"], w["n"], fractal=True)
     S = random_walk_series(w["seed"], w["R"], w["T"], sigma0=w["sigma"]).astype(np.float32)
     N = w["N"]
@@ -281,7 +281,7 @@ def run_series(a, w, B, ctx, torch):
                 iterations_mean=float(iters.mean()), iterations_max=int(iters.max()),
                 converged=int((r["status"] == 0).sum()), steps=int(w["T"]), tile=list(shape),
                 frames_per_transition=10, precision_vs_f64=precision_table(ctx, B, m, S[0], N),
-                roofline=roofline(a.stage, stage_ms, stage_n, N, w["precision"], m.n_vertices, w["T"], "config3"))
+                roofline=roofline(a.stage, stage_ms, stage_n, N, w["precision"], m.n_vertices, w["T"], "series64_fractal200_2048"))
 
 
 def main():
@@ -289,7 +289,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fractal100_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--graph-iters", type=int, default=-8,
@@ -298,10 +298,10 @@ def main():
     ap.add_argument("--stage", default="sat_final", choices=sorted(KERNEL_SOURCES),
                     help="kernel timed with HIP events for the roofline")
     ap.add_argument("--profile-every", type=int, default=8, help="time one launch of the stage per this many iterations")
-    ap.add_argument("--no-series", action="store_true", help="skip the batched 64-step series (config 3)")
+    ap.add_argument("--no-series", action="store_true", help="skip the batched 64-step series of 2048^2 cartograms")
     ap.add_argument("--series-steps", type=int, default=1, help="timed repetitions of the batched series")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch (config 4)")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start (config 5)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch of 256 cartograms")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start at 512^2")
     ap.add_argument("--learned-maps", type=int, default=64, help="held-out maps of the learned comparison")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
@@ -361,15 +361,15 @@ def main():
     roof = roofline(a.stage, stage_ms, stage_n, N, w["precision"], m.n_vertices, 1, a.workload)
 
     series = None
-    if not a.no_series and a.workload == "config2":
-        series = run_series(a, WORKLOADS["config3"], B, ctx, torch)
+    if not a.no_series and a.workload == "fractal100_1024":
+        series = run_series(a, WORKLOADS["series64_fractal200_2048"], B, ctx, torch)
 
     uneven = None
-    if not a.no_uneven and a.workload == "config2":
+    if not a.no_uneven and a.workload == "fractal100_1024":
         uneven = run_uneven(a, B, ctx, torch)
 
     learned = None
-    if not a.no_learned and a.workload == "config2":
+    if not a.no_learned and a.workload == "fractal100_1024":
         learned = run_learned(a, B, ctx, torch)
 
     cpu = None

@@ -222,8 +222,8 @@ def _run1(ctx, gm, xy, N, s, prec=1, **kw):
     return _np(r["xy"])[0], r
 
 
-def test_per_iteration_parity_config1(ctx):
-    """Config 1 (32 regions, ~2k vertices, 256^2, 20 iterations): every
+def test_per_iteration_parity_256(ctx):
+    """The small workload (32 regions, ~2k vertices, 256^2, 20 iterations): every
     iteration replayed from the GPU's own state -- labels bit-exact and
     moved positions within 1e-6 of the oracle's step."""
     m = voronoi_map(1000, 32, 2000, fractal=False)
@@ -246,7 +246,7 @@ def test_per_iteration_parity_config1(ctx):
 
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
-def test_end_to_end_config1(ctx, prec):
+def test_end_to_end_256(ctx, prec):
     """20 iterations on the GPU against the FP64 oracle with a float32
     state: positions within 1e-5 of the domain width."""
     m = voronoi_map(1000, 32, 2000, fractal=False)
@@ -344,7 +344,7 @@ def test_shape_parameter(ctx):
 @pytest.mark.parametrize("shape", [(128, 32), (256, 32)])
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_integral_image_labels_2048(ctx, prec, shape):
-    """Labels + LUT at 2048^2 (config-3 size) for every accumulation mode."""
+    """Labels + LUT at 2048^2 (the size of the batched series) for every accumulation mode."""
     m = voronoi_map(3000, 200, 200000, fractal=True)
     N = 2048
     lab, cnt, _ = oc.rasterize(m.xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, N)
