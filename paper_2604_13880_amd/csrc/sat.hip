@@ -209,6 +209,77 @@ __device__ __forceinline__ Lc wave_inclusive_scan_dpp(Lc x) {
   return x;
 }
 
+// Inclusive scan within segments of SEG lanes (16, 32 or 48/64; a
+// segment starts at a 16-lane row): the row shifts, then the row-15
+// broadcast only into rows that continue a segment, the row-31 broadcast
+// only for segments longer than 32 lanes.
+template <int SEG, typename Lc>
+__device__ __forceinline__ Lc seg_inclusive_scan_dpp(Lc x) {
+  static_assert(SEG == 16 || SEG == 32 || SEG == 48 || SEG == 64, "segments are whole DPP rows");
+  x += dpp_take<0x111, 0xf>(x);
+  x += dpp_take<0x112, 0xf>(x);
+  x += dpp_take<0x114, 0xf>(x);
+  x += dpp_take<0x118, 0xf>(x);
+  if (SEG >= 32) x += dpp_take<0x142, 0xa>(x);
+  if (SEG >= 48) x += dpp_take<0x143, 0xc>(x);
+  return x;
+}
+
+// One sub-band of kSub_Rows rows of a W-column strip, one row per segment
+// of SEG lanes, 8 consecutive columns per lane: wavefront w holds rows
+// w*RPP .. w*RPP+RPP-1.  The labels (or densities) of the next sub-band
+// are loaded while the current one is scanned.
+template <bool DENSE, int W, int NW>
+struct RowStage {
+  static constexpr int LPR = W / 8;                    // lanes per row
+  static constexpr int SEG = (LPR + 15) / 16 * 16;
+  static constexpr int RPP = 64 / SEG;                 // rows per wavefront
+  static_assert(W % 8 == 0 && SEG <= 64 && NW * RPP == kSub_Rows, "one pass covers the sub-band");
+  u32x4_t lab;
+  f32x4_t da, db;
+  bool ok;
+  bool act;    // the lane holds a chunk of a row of the sub-band
+  int g, li;   // row of the sub-band, chunk of the row
+
+  __device__ __forceinline__ void init() {
+    const int lane = threadIdx.x & 63;
+    g = (threadIdx.x >> 6) * RPP + lane / SEG;
+    li = lane % SEG;
+    act = lane / SEG < RPP && li < LPR;   // g < kSub_Rows
+  }
+  __device__ __forceinline__ void load(const InstG& I, int xs, int y) {
+    const int N = I.N, q = y + g, p = xs + 8 * li;
+    ok = act && q < N && p >= 0 && p < N;   // p, N multiples of 8: whole chunks
+    if (ok) {
+      const int64_t at = (int64_t)q * N + p;
+      if (DENSE) {
+        da = *(g_ptr<const f32x4_t>)(I.density + at);
+        db = *(g_ptr<const f32x4_t>)(I.density + at + 4);
+      } else {
+        lab = *(g_ptr<const u32x4_t>)(I.labels + at);
+      }
+    }
+  }
+  __device__ __forceinline__ void values(const InstG& I, float v[8]) const {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = 0.f;
+    if (!ok) return;
+    if (DENSE) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] = da[e];
+        v[4 + e] = db[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int lb = (int)((lab[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        v[e] = lb < I.n_lut ? I.lut[lb] : 0.f;   // labels outside the LUT carry no mass
+      }
+    }
+  }
+};
+
 template <typename A, typename Lc>
 __device__ __forceinline__ void acc_add_local(A& a, Lc x) { acc_add(a, x); }
 template <>
@@ -482,13 +553,12 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   constexpr int NW = TW / 64, SB = kSub_Rows;
   constexpr int XW = TW + 2 * TH;          // columns x0-TH .. x0+TW+TH-1
   constexpr int NSL = TW + TH + 1;         // anti-diagonal / diagonal slots
-  constexpr int E = XW / 64 + 1;           // strip columns per lane in the row scans
   const int64_t nb = B.off_tiles[B.n];
   const int64_t b = xcd_block(blockIdx.x, nb);
   const int k = find_inst(B.off_tiles, B.n, b);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  __shared__ float ds[SB][XW];
+  __shared__ __align__(16) float ds[SB][XW];   // rows of 8-column chunks, stored 16 B at a time
   __shared__ Lc Ml[SB][XW];                // Mloc of the sub-band's rows
   __shared__ Lc la_s[SB][NSL];
   __shared__ Lc lb_s[SB][NSL];
@@ -501,8 +571,6 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int tile = (int)(b - B.off_tiles[k]);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
-  const bool lut_lds = false;        // LUT read through the cache: more blocks fit in LDS
-  const float* lut_s = nullptr;
   g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
   g_ptr<const Cy> carry = (g_ptr<const Cy>)I.carry;
   // carries entering the tile
@@ -543,36 +611,62 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   A bsum;                  // sum of the row carries of the rows done
   acc_zero(bsum);
   Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0;
-  Stager<DENSE, SB, XW, TW> stg;
+  // T of the rows of sub-band r0, from the slot sums of its sweep
+  auto t_pass = [&](int r0) {
+#pragma unroll
+    for (int rr = 0; rr < SB; ++rr) {
+      const int r = r0 + rr, j = y0 + r + 1;
+      if (j > N) break;
+      const int64_t row = (int64_t)j * pitch;
+      {
+        const int sa = t + r + 1, sb = t + TH - 1 - r;
+        A v = acc_sub(ca_s[sa], cb_s[sb]);
+        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+        if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
+        else T[row + i] = to_store(v);
+      }
+      if (extra) {
+        const int sa = TW + r + 1, sb = TW + TH - 1 - r;
+        A v = acc_sub(ca_s[sa], cb_s[sb]);
+        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+        if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
+        else T[row + N] = to_store(v);
+      }
+    }
+  };
+  typedef RowStage<DENSE, XW, NW> Stage;
+  Stage stg;
+  stg.init();
   stg.load(I, x0 - TH, y0);
   for (int r0 = 0; r0 < TH; r0 += SB) {
-    __syncthreads();
-    stg.store(I, lut_s, lut_lds, ds);
-    if (r0 + SB < TH) stg.load(I, x0 - TH, y0 + r0 + SB);   // next sub-band in flight
-    __syncthreads();
-    // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, one
-    // wavefront per row, lanes holding E consecutive columns
-    for (int rr = w; rr < SB; rr += NW) {
-      Lc dv[E], loc = 0;
+    // T of the previous sub-band; then this sub-band's densities and
+    // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, each
+    // row scanned by one segment of a wavefront (8 columns per lane)
+    if (r0 > 0) t_pass(r0 - SB);
+    {
+      float dv[8];
+      stg.values(I, dv);
+      if (r0 + SB < TH) stg.load(I, x0 - TH, y0 + r0 + SB);   // next sub-band in flight
+      Lc loc = 0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int c = lane * E + e;
-        dv[e] = c < XW ? (Lc)ds[rr][c] : (Lc)0;
-        loc += dv[e];
-      }
-      const Lc x = wave_inclusive_scan_dpp(loc);
-      Lc run = x - loc;                    // exclusive prefix of the lane
-      Lc lv[E];
+      for (int e = 0; e < 8; ++e) loc += (Lc)dv[e];
+      const Lc x = seg_inclusive_scan_dpp<Stage::SEG>(loc);
+      const Lc ex = x - loc;                                  // exclusive prefix of the lane in its row
+      const int seg0 = lane - stg.li;
+      const Lc l0 = __shfl(ex, seg0 + TH / 8, 64);            // prefix at strip column TH (TH % 8 == 0)
+      if (stg.act) {
+        Lc run = ex - l0;
+        Lc mv[8];
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        lv[e] = run;
-        run += dv[e];
-      }
-      const Lc l0 = __shfl(lv[TH % E], TH / E, 64);   // prefix at strip column TH
+        for (int e = 0; e < 8; ++e) {
+          mv[e] = run + (Lc)0.5 * (Lc)dv[e];
+          run += (Lc)dv[e];
+        }
+        const int c = 8 * stg.li;
+        *(f32x4_t*)&ds[stg.g][c] = f32x4_t{dv[0], dv[1], dv[2], dv[3]};
+        *(f32x4_t*)&ds[stg.g][c + 4] = f32x4_t{dv[4], dv[5], dv[6], dv[7]};
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int c = lane * E + e;
-        if (c < XW) Ml[rr][c] = (lv[e] - l0) + (Lc)0.5 * dv[e];
+        for (int e = 0; e < 8; ++e) Ml[stg.g][c + e] = mv[e];
       }
     }
     __syncthreads();
@@ -610,27 +704,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < SB; ++rr) {
-      const int r = r0 + rr, j = y0 + r + 1;
-      if (j > N) break;
-      const int64_t row = (int64_t)j * pitch;
-      {
-        const int sa = t + r + 1, sb = t + TH - 1 - r;
-        A v = acc_sub(ca_s[sa], cb_s[sb]);
-        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
-        else T[row + i] = to_store(v);
-      }
-      if (extra) {
-        const int sa = TW + r + 1, sb = TW + TH - 1 - r;
-        A v = acc_sub(ca_s[sa], cb_s[sb]);
-        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
-        else T[row + N] = to_store(v);
-      }
-    }
   }
+  t_pass(TH - SB);
 }
 
 // host launchers --------------------------------------------------------------
