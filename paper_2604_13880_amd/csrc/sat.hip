@@ -225,6 +225,17 @@ __device__ __forceinline__ Lc seg_inclusive_scan_dpp(Lc x) {
   return x;
 }
 
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+// Eight consecutive LDS values (16-byte aligned) in 16-byte stores.
+__device__ __forceinline__ void store8(float* p, const float v[8]) {
+  *(f32x4_t*)p = f32x4_t{v[0], v[1], v[2], v[3]};
+  *(f32x4_t*)(p + 4) = f32x4_t{v[4], v[5], v[6], v[7]};
+}
+__device__ __forceinline__ void store8(double* p, const double v[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) *(f64x2_t*)(p + e) = f64x2_t{v[e], v[e + 1]};
+}
+
 // One sub-band of kSub_Rows rows of a W-column strip, one row per segment
 // of SEG lanes, 8 consecutive columns per lane: wavefront w holds rows
 // w*RPP .. w*RPP+RPP-1.  The labels (or densities) of the next sub-band
@@ -558,8 +569,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int k = find_inst(B.off_tiles, B.n, b);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  __shared__ __align__(16) float ds[SB][XW];   // rows of 8-column chunks, stored 16 B at a time
-  __shared__ Lc Ml[SB][XW];                // Mloc of the sub-band's rows
+  __shared__ __align__(16) float ds[SB][TW];   // densities of the node columns x0 .. x0+TW-1
+  __shared__ __align__(16) Lc Ml[SB][XW];      // Mloc of the sub-band's rows
   __shared__ Lc la_s[SB][NSL];
   __shared__ Lc lb_s[SB][NSL];
   __shared__ A ca_s[NSL];                  // TAc - TBc pairs are formed from these
@@ -662,11 +673,12 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
           mv[e] = run + (Lc)0.5 * (Lc)dv[e];
           run += (Lc)dv[e];
         }
-        const int c = 8 * stg.li;
-        *(f32x4_t*)&ds[stg.g][c] = f32x4_t{dv[0], dv[1], dv[2], dv[3]};
-        *(f32x4_t*)&ds[stg.g][c + 4] = f32x4_t{dv[4], dv[5], dv[6], dv[7]};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Ml[stg.g][c + e] = mv[e];
+        const int c = 8 * stg.li;                 // chunks never straddle column TH or TH+TW
+        if (c >= TH && c < TH + TW) {
+          *(f32x4_t*)&ds[stg.g][c - TH] = f32x4_t{dv[0], dv[1], dv[2], dv[3]};
+          *(f32x4_t*)&ds[stg.g][c - TH + 4] = f32x4_t{dv[4], dv[5], dv[6], dv[7]};
+        }
+        store8(&Ml[stg.g][c], mv);   // 16 B stores: lanes 32 B apart would conflict as scalars
       }
     }
     __syncthreads();
@@ -674,7 +686,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;
       acc_addv(bsum, rc_s[r]);
-      rsum += Ml[rr][t + TH] - (Lc)0.5 * (Lc)ds[rr][t + TH];   // Rloc at node column i
+      rsum += Ml[rr][t + TH] - (Lc)0.5 * (Lc)ds[rr][t];        // Rloc at node column i
       if (extra) rsumN += Ml[rr][TW + TH];                     // column N lies outside: d = 0
       if (j <= N) {
         {
