@@ -96,6 +96,7 @@ struct Stager {
 };
 
 constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of the tile)
+constexpr int kReduce_Rows = 8;   // rows per sub-band of the reduce pass (every thread loads)
 
 // Row prefix sums of one sub-band: M[rr][c] = base + (L(c) - L(c0)) + d(c)/2
 // where L is the exclusive prefix of the row over the staged columns and
@@ -311,8 +312,9 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int k = find_inst(B.off_tiles, B.n, b);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  constexpr int NW = TW / 64, D = TW + TH - 1, SB = kSub_Rows, E = TW / 64;
+  constexpr int NW = TW / 64, D = TW + TH - 1, SB = (kReduce_Rows < TH ? kReduce_Rows : TH), E = TW / 64;
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
+  static_assert(TH % SB == 0, "whole sub-bands");
   __shared__ float ds[SB][TW];
   __shared__ A rsum[TH];
   __shared__ A wt[NW];
