@@ -131,6 +131,12 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   P.th = th;
   P.dense = dense;
   P.inst.assign(n, Inst{});
+  // the integral-image writer fills whole tile rows: every texture holds a
+  // whole number of them (powers of two, tiles capped by cap_shape)
+  if (nd.sat)
+    for (const Spec& s : specs)
+      if (th <= 0 || s.N % th != 0 || tw > std::max(64, s.N))
+        return fail(c, CG_EINVAL, "tile shape does not fit a texture of the batch");
   P.il = nd.sat && !dense;
   for (const Spec& s : specs) P.il = P.il && !s.S && !s.T;
   // scratch layout

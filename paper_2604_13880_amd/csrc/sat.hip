@@ -247,46 +247,54 @@ struct RowStage {
   static constexpr int SEG = (LPR + 15) / 16 * 16;
   static constexpr int RPP = 64 / SEG;                 // rows per wavefront
   static_assert(W % 8 == 0 && SEG <= 64 && NW * RPP == kSub_Rows, "one pass covers the sub-band");
+  // Labels and LUT entries are read with buffer loads: an offset past the
+  // descriptor's byte count reads 0, so chunks outside the texture and
+  // labels outside the LUT need no branch (kOut marks them).
+  static constexpr uint32_t kOut = 0x80000000u;
+  __amdgpu_buffer_rsrc_t lab_rs, lut_rs;
   u32x4_t lab;
   f32x4_t da, db;
   bool ok;
   bool act;    // the lane holds a chunk of a row of the sub-band
   int g, li;   // row of the sub-band, chunk of the row
 
-  __device__ __forceinline__ void init() {
+  __device__ __forceinline__ void init(const InstG& I) {
     const int lane = threadIdx.x & 63;
     g = (threadIdx.x >> 6) * RPP + lane / SEG;
     li = lane % SEG;
     act = lane / SEG < RPP && li < LPR;   // g < kSub_Rows
+    if (!DENSE) {
+      lab_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.labels, (short)0, (int)(2 * (int64_t)I.N * I.N), 0x00020000);
+      lut_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.lut, (short)0, 4 * I.n_lut, 0x00020000);
+    }
   }
   __device__ __forceinline__ void load(const InstG& I, int xs, int y) {
     const int N = I.N, q = y + g, p = xs + 8 * li;
     ok = act && q < N && p >= 0 && p < N;   // p, N multiples of 8: whole chunks
-    if (ok) {
-      const int64_t at = (int64_t)q * N + p;
-      if (DENSE) {
+    if (DENSE) {
+      if (ok) {
+        const int64_t at = (int64_t)q * N + p;
         da = *(g_ptr<const f32x4_t>)(I.density + at);
         db = *(g_ptr<const f32x4_t>)(I.density + at + 4);
-      } else {
-        lab = *(g_ptr<const u32x4_t>)(I.labels + at);
       }
+    } else {
+      const uint32_t off = ok ? (uint32_t)(2 * ((int64_t)q * N + p)) : kOut;   // N^2 * 2 < 2^31
+      lab = __builtin_amdgcn_raw_buffer_load_b128(lab_rs, (int)off, 0, 0);
     }
   }
   __device__ __forceinline__ void values(const InstG& I, float v[8]) const {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = 0.f;
-    if (!ok) return;
     if (DENSE) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        v[e] = da[e];
-        v[4 + e] = db[e];
+        v[e] = ok ? da[e] : 0.f;
+        v[4 + e] = ok ? db[e] : 0.f;
       }
     } else {
+      const uint32_t out = ok ? 0u : kOut;   // zero mass outside the texture
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int lb = (int)((lab[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        v[e] = lb < I.n_lut ? I.lut[lb] : 0.f;   // labels outside the LUT carry no mass
+        const uint32_t lb = (lab[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+        v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(lut_rs, (int)((lb << 2) | out), 0, 0));
       }
     }
   }
@@ -589,7 +597,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   // carries entering the tile
   A stop, stopN;
   from_carry(stop, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
-  const bool extra = (x0 + TW == N) && t == 0;   // the tile column that ends at node column N
+  const bool xcol = x0 + TW == N;                 // the tile column that ends at node column N (block-uniform)
+  const bool extra = xcol && t == 0;
   if (extra) from_carry(stopN, carry[L.Stop + (int64_t)ty * (L.NX + 1) + N]);
   else acc_zero(stopN);
   for (int sl = t; sl < NSL; sl += TW) {
@@ -621,35 +630,39 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   St sv[SB], svN[SB];      // S of the sub-band's rows, stored with T (interleaved tables)
   const int s1 = t + TW;
   const bool has1 = s1 < NSL;
-  A bsum;                  // sum of the row carries of the rows done
-  acc_zero(bsum);
+  A sb = stop, sbN = stopN;   // column carry plus the row carries of the rows done
   Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0;
   // T of the rows of sub-band r0, from the slot sums of its sweep
   auto t_pass = [&](int r0) {
+    // rows without branches between them, so their LDS reads can be batched
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
-      const int r = r0 + rr, j = y0 + r + 1;
-      if (j > N) break;
+      const int r = r0 + rr, j = y0 + r + 1;   // j <= N: N is a multiple of TH
       const int64_t row = (int64_t)j * pitch;
-      {
-        const int sa = t + r + 1, sb = t + TH - 1 - r;
-        A v = acc_sub(ca_s[sa], cb_s[sb]);
-        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
-        else T[row + i] = to_store(v);
-      }
-      if (extra) {
-        const int sa = TW + r + 1, sb = TW + TH - 1 - r;
-        A v = acc_sub(ca_s[sa], cb_s[sb]);
-        acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-        if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
-        else T[row + N] = to_store(v);
+      const int sa = t + r + 1, sb = t + TH - 1 - r;
+      A v = acc_sub(ca_s[sa], cb_s[sb]);
+      acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+      if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
+      else T[row + i] = to_store(v);
+    }
+    if (xcol) {
+      if (t == 0) {
+#pragma unroll
+        for (int rr = 0; rr < SB; ++rr) {
+          const int r = r0 + rr;
+          const int64_t row = (int64_t)(y0 + r + 1) * pitch;
+          const int sa = TW + r + 1, sb = TW + TH - 1 - r;
+          A v = acc_sub(ca_s[sa], cb_s[sb]);
+          acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+          if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
+          else T[row + N] = to_store(v);
+        }
       }
     }
   };
   typedef RowStage<DENSE, XW, NW> Stage;
   Stage stg;
-  stg.init();
+  stg.init(I);
   stg.load(I, x0 - TH, y0);
   for (int r0 = 0; r0 < TH; r0 += SB) {
     // T of the previous sub-band; then this sub-band's densities and
@@ -687,34 +700,39 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;
-      acc_addv(bsum, rc_s[r]);
+      acc_addv(sb, rc_s[r]);
       rsum += Ml[rr][t + TH] - (Lc)0.5 * (Lc)ds[rr][t];        // Rloc at node column i
-      if (extra) rsumN += Ml[rr][TW + TH];                     // column N lies outside: d = 0
-      if (j <= N) {
-        {
-          A v = stop;
-          acc_addv(v, bsum);
-          acc_add_local(v, rsum);
-          sv[rr] = (St)to_store(v);
-          if (!IL) S[(int64_t)j * pitch + i] = sv[rr];
-        }
-        if (extra) {
-          A v = stopN;
-          acc_addv(v, bsum);
-          acc_add_local(v, rsumN);
-          svN[rr] = (St)to_store(v);
-          if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
-        }
-      }
+      A v = sb;
+      acc_add_local(v, rsum);
+      sv[rr] = (St)to_store(v);
+      if (!IL) S[(int64_t)j * pitch + i] = sv[rr];
       la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
       lb0 += Ml[rr][t + r];                // diagonal slot t
       la_s[rr][t] = la0;
       lb_s[rr][t] = lb0;
-      if (has1) {
+    }
+    if (has1) {                            // slots t + TW
+#pragma unroll
+      for (int rr = 0; rr < SB; ++rr) {
+        const int r = r0 + rr;
         la1 += Ml[rr][s1 + TH - 1 - r];
         lb1 += Ml[rr][s1 + r];
         la_s[rr][s1] = la1;
         lb_s[rr][s1] = lb1;
+      }
+    }
+    if (xcol) {
+      if (t == 0) {
+#pragma unroll
+        for (int rr = 0; rr < SB; ++rr) {
+          const int r = r0 + rr, j = y0 + r + 1;
+          acc_addv(sbN, rc_s[r]);
+          rsumN += Ml[rr][TW + TH];                             // column N lies outside: d = 0
+          A v = sbN;
+          acc_add_local(v, rsumN);
+          svN[rr] = (St)to_store(v);
+          if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
+        }
       }
     }
     __syncthreads();
