@@ -135,7 +135,8 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   // whole number of them (powers of two, tiles capped by cap_shape)
   if (nd.sat)
     for (const Spec& s : specs)
-      if (th <= 0 || s.N % th != 0 || tw > std::max(64, s.N))
+      if (th <= 0 || s.N % th != 0 || tw > std::max(64, s.N) ||
+          2 * store_size(prec) * (size_t)(s.N + 1) * pitch_of(s.N) >= ((size_t)1 << 31))
         return fail(c, CG_EINVAL, "tile shape does not fit a texture of the batch");
   P.il = nd.sat && !dense;
   for (const Spec& s : specs) P.il = P.il && !s.S && !s.T;

@@ -42,9 +42,18 @@ template <bool DENSE, int SBR, int W, int NT>
 struct Stager {
   static constexpr int CH = W / 8;
   static constexpr int NC = (SBR * CH + NT - 1) / NT;   // chunks per thread
+  static constexpr uint32_t kOut = 0x80000000u;         // buffer offset that reads 0
   u32x4_t lab[NC];
   f32x4_t da[DENSE ? NC : 1], db[DENSE ? NC : 1];
   bool ok[NC];
+  __amdgpu_buffer_rsrc_t lab_rs, lut_rs;
+
+  __device__ __forceinline__ void init(const InstG& I) {
+    if (!DENSE) {
+      lab_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.labels, (short)0, (int)(2 * (int64_t)I.N * I.N), 0x00020000);
+      lut_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.lut, (short)0, 4 * I.n_lut, 0x00020000);
+    }
+  }
 
   __device__ __forceinline__ void load(const InstG& I, int xs, int y0) {
     const int N = I.N;
@@ -54,18 +63,21 @@ struct Stager {
       const int r = c / CH, k = c - r * CH;
       const int q = y0 + r, p = xs + 8 * k;
       ok[n] = c < SBR * CH && q < N && p >= 0 && p < N;
-      if (ok[n]) {
-        const int64_t at = (int64_t)q * N + p;
-        if (DENSE) {
+      if (DENSE) {
+        if (ok[n]) {
+          const int64_t at = (int64_t)q * N + p;
           da[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at);
           db[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at + 4);
-        } else {
-          lab[n] = *(g_ptr<const u32x4_t>)(I.labels + at);
         }
+      } else {
+        const uint32_t off = ok[n] ? (uint32_t)(2 * ((int64_t)q * N + p)) : kOut;
+        lab[n] = __builtin_amdgcn_raw_buffer_load_b128(lab_rs, (int)off, 0, 0);
       }
     }
   }
 
+  // Densities of the staged chunks into ds: LUT lookups from LDS (clamped
+  // index and a select) or by range-checked buffer loads; no branches.
   __device__ __forceinline__ void store(const InstG& I, const float* lut_s, bool lut_lds, float (*ds)[W]) const {
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
@@ -73,24 +85,30 @@ struct Stager {
       if (c >= SBR * CH) break;
       const int r = c / CH, k = c - r * CH;
       float v[8];
-      if (!ok[n]) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = 0.f;
-      } else if (DENSE) {
+      if (DENSE) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          v[e] = da[DENSE ? n : 0][e];
-          v[4 + e] = db[DENSE ? n : 0][e];
+          v[e] = ok[n] ? da[DENSE ? n : 0][e] : 0.f;
+          v[4 + e] = ok[n] ? db[DENSE ? n : 0][e] : 0.f;
         }
-      } else {
+      } else if (lut_lds) {
+        const int nl = ok[n] ? I.n_lut : 0;   // outside the texture: no mass
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int lb = (int)((lab[n][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-          v[e] = lb < I.n_lut ? (lut_lds ? lut_s[lb] : I.lut[lb]) : 0.f;  // labels outside the LUT carry no mass
+          const float x = lut_s[lb < kLutLds ? lb : 0];
+          v[e] = lb < nl ? x : 0.f;   // labels outside the LUT carry no mass
+        }
+      } else {
+        const uint32_t out = ok[n] ? 0u : kOut;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t lb = (lab[n][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+          v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(lut_rs, (int)((lb << 2) | out), 0, 0));
         }
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ds[r][8 * k + e] = v[e];
+      *(f32x4_t*)&ds[r][8 * k] = f32x4_t{v[0], v[1], v[2], v[3]};
+      *(f32x4_t*)&ds[r][8 * k + 4] = f32x4_t{v[4], v[5], v[6], v[7]};
     }
   }
 };
@@ -227,6 +245,14 @@ __device__ __forceinline__ Lc seg_inclusive_scan_dpp(Lc x) {
 }
 
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+// Buffer store of a 4, 8 or 16-byte value at voff + soff bytes.
+template <typename T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs, voff, soff, 0);
+  else if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, voff, soff, 0);
+  else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, soff, 0);
+}
 // Eight consecutive LDS values (16-byte aligned) in 16-byte stores.
 __device__ __forceinline__ void store8(float* p, const float v[8]) {
   *(f32x4_t*)p = f32x4_t{v[0], v[1], v[2], v[3]};
@@ -323,7 +349,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   constexpr int NW = TW / 64, D = TW + TH - 1, SB = (kReduce_Rows < TH ? kReduce_Rows : TH), E = TW / 64;
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
   static_assert(TH % SB == 0, "whole sub-bands");
-  __shared__ float ds[SB][TW];
+  __shared__ __align__(16) float ds[SB][TW];
   __shared__ A rsum[TH];
   __shared__ A wt[NW];
   __shared__ float lut_s[kLutLds];
@@ -340,6 +366,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int c1 = t + TW;
   const bool has1 = c1 < D;
   Stager<DENSE, SB, TW, TW> stg;
+  stg.init(I);
   stg.load(I, x0, y0);
   for (int r0 = 0; r0 < TH; r0 += SB) {
     __syncthreads();
@@ -350,22 +377,30 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
       Lc v = 0;
 #pragma unroll
       for (int e = 0; e < E; ++e) v += (Lc)ds[rr][lane + 64 * e];
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-      if (lane == 0) acc_zero(rsum[r0 + rr]), acc_add_local(rsum[r0 + rr], v);
+      v = wave_inclusive_scan_dpp(v);       // lane 63 holds the row total
+      if (lane == 63) acc_zero(rsum[r0 + rr]), acc_add_local(rsum[r0 + rr], v);
     }
+    // branch-free: clamped indices and selects
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr;
       col += (Lc)ds[rr][t];
       const int ca = t - r;                 // anti-diagonal slot t meets row r here
-      if (ca >= 0) ha0 += (Lc)ds[rr][ca];
+      const Lc va = (Lc)ds[rr][ca < 0 ? 0 : ca];
+      ha0 += ca >= 0 ? va : (Lc)0;
       const int cb = t + r - TH + 1;        // diagonal slot t
-      if (cb >= 0) hb0 += (Lc)ds[rr][cb];
-      if (has1) {                           // slots t + TW (always right of column 0)
+      const Lc vb = (Lc)ds[rr][cb < 0 ? 0 : cb];
+      hb0 += cb >= 0 ? vb : (Lc)0;
+    }
+    if (has1) {                             // slots t + TW (always right of column 0)
+#pragma unroll
+      for (int rr = 0; rr < SB; ++rr) {
+        const int r = r0 + rr;
         const int ca1 = c1 - r, cb1 = c1 + r - TH + 1;
-        if (ca1 < TW) ha1 += (Lc)ds[rr][ca1];
-        if (cb1 < TW) hb1 += (Lc)ds[rr][cb1];
+        const Lc va = (Lc)ds[rr][ca1 < TW ? ca1 : TW - 1];
+        const Lc vb = (Lc)ds[rr][cb1 < TW ? cb1 : TW - 1];
+        ha1 += ca1 < TW ? va : (Lc)0;
+        hb1 += cb1 < TW ? vb : (Lc)0;
       }
     }
   }
@@ -629,21 +664,25 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   }
   St sv[SB], svN[SB];      // S of the sub-band's rows, stored with T (interleaved tables)
   const int s1 = t + TW;
-  const bool has1 = s1 < NSL;
+  const bool has1 = s1 < NSL - 1;          // slot TW+TH serves node column N only: the extra thread's
   A sb = stop, sbN = stopN;   // column carry plus the row carries of the rows done
-  Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0;
+  Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0, laN = 0;
+  // stores of whole rows: buffer stores, the row offset in a scalar register
+  // (tables are below 2 GiB: checked on the host)
+  const int64_t tab_bytes = (int64_t)(N + 1) * I.pitch * (IL ? (int64_t)sizeof(St2) : (int64_t)sizeof(St));
+  const __amdgpu_buffer_rsrc_t s_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.S, (short)0, (int)tab_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t t_rs = __builtin_amdgcn_make_buffer_rsrc(IL ? (void*)I.S : (void*)I.T, (short)0, (int)tab_bytes, 0x00020000);
   // T of the rows of sub-band r0, from the slot sums of its sweep
   auto t_pass = [&](int r0) {
     // rows without branches between them, so their LDS reads can be batched
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;   // j <= N: N is a multiple of TH
-      const int64_t row = (int64_t)j * pitch;
       const int sa = t + r + 1, sb = t + TH - 1 - r;
       A v = acc_sub(ca_s[sa], cb_s[sb]);
       acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-      if (IL) ST[row + i] = St2{sv[rr], (St)to_store(v)};
-      else T[row + i] = to_store(v);
+      if (IL) bstore(St2{sv[rr], (St)to_store(v)}, t_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
+      else bstore((St)to_store(v), t_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
     }
     if (xcol) {
       if (t == 0) {
@@ -705,7 +744,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       A v = sb;
       acc_add_local(v, rsum);
       sv[rr] = (St)to_store(v);
-      if (!IL) S[(int64_t)j * pitch + i] = sv[rr];
+      if (!IL) bstore(sv[rr], s_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
       la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
       lb0 += Ml[rr][t + r];                // diagonal slot t
       la_s[rr][t] = la0;
@@ -728,6 +767,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
           const int r = r0 + rr, j = y0 + r + 1;
           acc_addv(sbN, rc_s[r]);
           rsumN += Ml[rr][TW + TH];                             // column N lies outside: d = 0
+          laN += Ml[rr][TW + 2 * TH - 1 - r];                  // anti-diagonal slot TW+TH
+          la_s[rr][TW + TH] = laN;
           A v = sbN;
           acc_add_local(v, rsumN);
           svN[rr] = (St)to_store(v);
