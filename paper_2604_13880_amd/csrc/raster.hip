@@ -176,6 +176,15 @@ __device__ __forceinline__ void claims_toggle(Claims& c, int r, bool& over) {
   }
 }
 
+// The set {a} (empty for a = 0) toggled by b and by c (0 toggles
+// nothing) holds at most one region.
+__device__ __forceinline__ bool single_claim_ok(uint32_t a, uint32_t b, uint32_t c) {
+  const int na = a != 0u ? ((1 + (b == a) + (c == a)) & 1) : 0;
+  const int nb = (b != 0u && b != a) ? ((1 + (c == b)) & 1) : 0;
+  const int nc = (c != 0u && c != a && c != b) ? 1 : 0;
+  return na + nb + nc <= 1;
+}
+
 __device__ __forceinline__ void claims_label(const Claims& c, int& lab, int& n) {
   if (!c.multi) {
     lab = c.cur;
@@ -189,6 +198,23 @@ __device__ __forceinline__ void claims_label(const Claims& c, int& lab, int& n) 
     lab = max(lab, c.set[i]);
     n += c.set[i] != 0;
   }
+}
+
+// Bitonic sort of one 32-bit key per lane over the first SZ lanes
+// (ascending there; lanes beyond SZ sort among themselves).
+template <int SZ>
+__device__ __forceinline__ uint32_t bitonic_sort(uint32_t key, int lane) {
+#pragma unroll
+  for (int size = 2; size <= SZ; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)key, stride, 64);
+      const bool up = (lane & size) == 0;      // ascending half of this bitonic sequence
+      const bool low = (lane & stride) == 0;   // lower partner
+      key = (up == low) ? min(key, other) : max(key, other);
+    }
+  }
+  return key;
 }
 
 // One wavefront per row.  Crossings sorted by p0; t = A xor B for every
@@ -231,27 +257,18 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
     }
     __syncthreads();
     if (row_ok && cnt <= 64) {
-      // bitonic sort of (p0, slot) keys across the wavefront's lanes
-      const uint64_t rec = lane < (int)cnt ? xs[w][lane] : 0ull;
-      uint64_t key = lane < (int)cnt ? (((rec & 0xFFFFull) << 8) | (uint64_t)lane) : ~0ull;
-      uint64_t val = rec;
-#pragma unroll
-      for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          const uint64_t ok2 = __shfl_xor(key, stride, 64);
-          const uint64_t ov = __shfl_xor(val, stride, 64);
-          const bool up = (lane & size) == 0;          // ascending half of this bitonic sequence
-          const bool low = (lane & stride) == 0;        // lower partner
-          const bool take_min = (up == low);
-          const bool swap = take_min ? (ok2 < key) : (ok2 > key);
-          if (swap) {
-            key = ok2;
-            val = ov;
-          }
-        }
-      }
-      if (lane < (int)cnt) srt[w][lane] = val;
+      // bitonic sort of 32-bit keys (p0, slot) over the smallest power of
+      // two of lanes that holds the row's crossings; the record follows
+      // from the slot
+      const uint32_t key0 = lane < (int)cnt ? (((uint32_t)(xs[w][lane] & 0xFFFFull) << 6) | (uint32_t)lane) : ~0u;
+      uint32_t key;
+      if (cnt <= 2) key = bitonic_sort<2>(key0, lane);
+      else if (cnt <= 4) key = bitonic_sort<4>(key0, lane);
+      else if (cnt <= 8) key = bitonic_sort<8>(key0, lane);
+      else if (cnt <= 16) key = bitonic_sort<16>(key0, lane);
+      else if (cnt <= 32) key = bitonic_sort<32>(key0, lane);
+      else key = bitonic_sort<64>(key0, lane);
+      if (lane < (int)cnt) srt[w][lane] = xs[w][key & 63u];
     } else if (row_ok) {  // rank sort by (p0, slot)
       for (uint32_t i = lane; i < cnt; i += 64) {
         const uint64_t a = xs[w][i];
@@ -285,7 +302,14 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       // on the claim set before it ({xb}, or empty when xb = 0): the xor
       // labels stay exact iff at most one region claims afterwards
       bool ok = !bad;
-      if (last) {
+      const uint32_t pprev = __shfl_up(p0, 1, 64);
+      const bool first = live && (lane == 0 || pprev != p0);
+      if (__all(!last || first)) {
+        // every group is a single crossing: the claim set before it is {xb}
+        // (empty when xb = 0), after it the odd-multiplicity members of
+        // {xb, ra, rb}; the xor label is exact iff at most one remains
+        if (last) ok = ok && single_claim_ok(x ^ ra ^ rb, ra, rb);
+      } else if (last) {
         uint32_t xb = x;
         int j = lane, members = 0;
         while (true) {
@@ -414,24 +438,45 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       // fill: spans 0..ngroups, the last span with start <= p holds pixel p
       const int nsp = (int)ngroups + 1;
       g_ptr<uint16_t> row = I.labels + (int64_t)q * N;
-      for (int p = lane * 8; p < N; p += 64 * 8) {
-        int lo = 0, hi = nsp;
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (sp_start[w][mid] <= p) lo = mid; else hi = mid;
-        }
-        uint16_t v[8];
-        const uint16_t l0 = sp_lab[w][lo];
-        const int next = lo + 1 < nsp ? (int)sp_start[w][lo + 1] : N;
-        if (next >= p + 8) {   // the 8 pixels lie in one run
+      int steps = 0;                       // binary-search steps over the spans (uniform)
+      while ((1 << steps) < nsp) ++steps;
+      constexpr int U = 4;                 // chunks searched in lockstep per lane
+      for (int pb = lane * 8; pb < N; pb += 64 * 8 * U) {
+        int los[U];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) v[c] = l0;
-        } else {
-          int s2 = lo;
+        for (int u = 0; u < U; ++u) los[u] = 0;
+        for (int st = 0, span = 1 << (steps > 0 ? steps - 1 : 0); st < steps; ++st, span >>= 1) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {   // invariant: sp_start[los] <= p
+            const int mid = los[u] + span;
+            const bool in = mid < nsp;
+            const int sp = sp_start[w][in ? mid : 0];
+            los[u] = (in && sp <= pb + u * 512) ? mid : los[u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+        const int p = pb + u * 512;
+        if (p >= N) break;
+        const int lo = los[u];
+        uint16_t v[8];
+        // the next three span starts (N past the last span), read together;
+        // the chunk's labels follow by selects when at most two spans start
+        // inside it
+        const int i1 = min(lo + 1, nsp - 1), i2 = min(lo + 2, nsp - 1), i3 = min(lo + 3, nsp - 1);
+        const int s1 = lo + 1 < nsp ? (int)sp_start[w][i1] : N;
+        const int s2 = lo + 2 < nsp ? (int)sp_start[w][i2] : N;
+        const int s3 = lo + 3 < nsp ? (int)sp_start[w][i3] : N;
+        const uint16_t l0 = sp_lab[w][lo], l1 = sp_lab[w][i1], l2 = sp_lab[w][i2];
+        if (s3 >= p + 8) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v[c] = p + c < s1 ? l0 : (p + c < s2 ? l1 : l2);
+        } else {               // three or more spans start in these 8 pixels
+          int sx = lo;
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
-            while (s2 + 1 < nsp && sp_start[w][s2 + 1] <= p + c) ++s2;
-            v[c] = sp_lab[w][s2];
+            while (sx + 1 < nsp && sp_start[w][sx + 1] <= p + c) ++sx;
+            v[c] = sp_lab[w][sx];
           }
         }
         typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -441,6 +486,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
         pk.z = v[4] | ((uint32_t)v[5] << 16);
         pk.w = v[6] | ((uint32_t)v[7] << 16);
         *(g_ptr<u32x4_t>)(row + p) = pk;     // N is a multiple of 8
+        }
       }
       if (lane == 0) I.row_cnt[q] = 0u;
     }
