@@ -100,25 +100,16 @@ __device__ __forceinline__ void t_uniform(F x, F y, F q1x, F q1y, F q2x, F q2y, 
   ty = h * (a * q1y + b * q2y + g * q3y + d * q4y + at + (bt + dt) * y);
 }
 
-// Steps 5 at one node: D = t(.; d) - t(.; d0) (eqs.(2)-(3)).
-// Table element (i, j) of S or T lives at [(j * pitch + i) * ST] (ST = 2 for
-// interleaved (S, T) pairs, 1 for separate tables).
-template <typename F, int ST>
-__device__ __forceinline__ void node_disp(g_ptr<const F> S, g_ptr<const F> T, g_ptr<const F> HA, g_ptr<const F> HB, int64_t pitch,
-                                          int N, F C, int i, int j, F& dx, F& dy) {
-  const F invN = F(1) / F(N);
-  const F x = F(i) * invN, y = F(j) * invN;
-  const F s = S[((int64_t)j * pitch + i) * ST];
-  const F siN = S[((int64_t)N * pitch + i) * ST];
-  const F sNj = S[((int64_t)j * pitch + N) * ST];
-  const F tt = T[((int64_t)j * pitch + i) * ST];
-  const F ha = HA[i + j];
-  const F hb = HB[j - i + N];
+// Step 5 at one node (x, y) = (i, j) / N: D = t(.; d) - t(.; d0)
+// (eqs.(2)-(3)) from the node's S and T, S at (i, N) and (N, j), the
+// diagonal marginals HA[i + j] and HB[j - i + N], the total C and 1/(2C).
+template <typename F>
+__device__ __forceinline__ void node_disp(F x, F y, F s, F tt, F siN, F sNj, F ha, F hb, F C, F inv2C, F& dx,
+                                          F& dy) {
   const F a = s, b = siN - s, dl = sNj - s, g = C - siN - sNj + s;
   const F at = tt, bt = ha - tt, dt = hb - tt, gt = C - ha - hb + tt;
   F q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y;
   anchors(x, y, q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y);
-  const F inv2C = F(1) / (F(2) * C);
   const F tx = (a * q1x + b * q2x + g * q3x + dl * q4x + (at + gt) * x + bt) * inv2C;
   const F ty = (a * q1y + b * q2y + g * q3y + dl * q4y + at + (bt + dt) * y) * inv2C;
   F ux, uy;
@@ -127,7 +118,23 @@ __device__ __forceinline__ void node_disp(g_ptr<const F> S, g_ptr<const F> T, g_
   dy = ty - uy;
 }
 
+// (S, T) of node (i, j): one load of the interleaved pair (ST = 2) or two.
+template <typename F, int ST>
+__device__ __forceinline__ void node_st(g_ptr<const F> S, g_ptr<const F> T, int64_t at, F& s, F& t) {
+  if (ST == 2) {
+    typedef F F2 __attribute__((ext_vector_type(2)));
+    const F2 v = *(g_ptr<const F2>)(S + 2 * at);
+    s = v[0];
+    t = v[1];
+  } else {
+    s = S[at];
+    t = T[at];
+  }
+}
+
 // Step 6: bilinear interpolation of D at each point, clamp to [0,1]^2.
+// The four corner nodes share their marginals: three consecutive HA and HB
+// values, two values of row N and two of column N.
 template <typename F, int ST>
 __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   const int k = find_inst(B.off_pts, B.n, blockIdx.x);
@@ -150,11 +157,24 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   g_ptr<const F> HB = (g_ptr<const F>)I.HB;
   const int64_t pitch = I.pitch;
   const F C = S[((int64_t)N * pitch + N) * ST];
+  const F inv2C = F(1) / (F(2) * C), invN = F(1) / fN;
+  const int64_t r0 = (int64_t)j0 * pitch + i0, r1 = r0 + pitch, rN = (int64_t)N * pitch + i0;
+  F s00, t00, s10, t10, s01, t01, s11, t11;
+  node_st<F, ST>(S, T, r0, s00, t00);
+  node_st<F, ST>(S, T, r0 + 1, s10, t10);
+  node_st<F, ST>(S, T, r1, s01, t01);
+  node_st<F, ST>(S, T, r1 + 1, s11, t11);
+  const F sN0 = S[rN * ST], sN1 = S[(rN + 1) * ST];                                   // (i0, N), (i0+1, N)
+  const F s0N = S[((int64_t)j0 * pitch + N) * ST], s1N = S[((int64_t)(j0 + 1) * pitch + N) * ST];   // (N, j0), (N, j0+1)
+  const int ia = i0 + j0, ib = j0 - i0 + N;
+  const F ha0 = HA[ia], ha1 = HA[ia + 1], ha2 = HA[ia + 2];
+  const F hb0 = HB[ib - 1], hb1 = HB[ib], hb2 = HB[ib + 1];
+  const F x0 = F(i0) * invN, x1 = F(i0 + 1) * invN, y0 = F(j0) * invN, y1 = F(j0 + 1) * invN;
   F d00x, d00y, d10x, d10y, d01x, d01y, d11x, d11y;
-  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0, j0, d00x, d00y);
-  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0 + 1, j0, d10x, d10y);
-  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0, j0 + 1, d01x, d01y);
-  node_disp<F, ST>(S, T, HA, HB, pitch, N, C, i0 + 1, j0 + 1, d11x, d11y);
+  node_disp<F>(x0, y0, s00, t00, sN0, s0N, ha0, hb1, C, inv2C, d00x, d00y);
+  node_disp<F>(x1, y0, s10, t10, sN1, s0N, ha1, hb0, C, inv2C, d10x, d10y);
+  node_disp<F>(x0, y1, s01, t01, sN0, s1N, ha1, hb2, C, inv2C, d01x, d01y);
+  node_disp<F>(x1, y1, s11, t11, sN1, s1N, ha2, hb1, C, inv2C, d11x, d11y);
   const F w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
   const F dx = w00 * d00x + w10 * d10x + w01 * d01x + w11 * d11x;
   const F dy = w00 * d00y + w10 * d10y + w01 * d01y + w11 * d11y;
