@@ -614,7 +614,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int k = find_inst(B.off_tiles, B.n, b);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  __shared__ __align__(16) float ds[SB][TW];   // densities of the node columns x0 .. x0+TW-1
+  __shared__ __align__(16) Lc Pn[SB][TW];      // exclusive row prefix (from strip column TH) at node columns
   __shared__ __align__(16) Lc Ml[SB][XW];      // Mloc of the sub-band's rows
   __shared__ Lc la_s[SB][NSL];
   __shared__ Lc lb_s[SB][NSL];
@@ -721,17 +721,15 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       const Lc l0 = __shfl(ex, seg0 + TH / 8, 64);            // prefix at strip column TH (TH % 8 == 0)
       if (stg.act) {
         Lc run = ex - l0;
-        Lc mv[8];
+        Lc mv[8], pv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
+          pv[e] = run;
           mv[e] = run + (Lc)0.5 * (Lc)dv[e];
           run += (Lc)dv[e];
         }
         const int c = 8 * stg.li;                 // chunks never straddle column TH or TH+TW
-        if (c >= TH && c < TH + TW) {
-          *(f32x4_t*)&ds[stg.g][c - TH] = f32x4_t{dv[0], dv[1], dv[2], dv[3]};
-          *(f32x4_t*)&ds[stg.g][c - TH + 4] = f32x4_t{dv[4], dv[5], dv[6], dv[7]};
-        }
+        if (c >= TH && c < TH + TW) store8(&Pn[stg.g][c - TH], pv);
         store8(&Ml[stg.g][c], mv);   // 16 B stores: lanes 32 B apart would conflict as scalars
       }
     }
@@ -740,7 +738,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;
       acc_addv(sb, rc_s[r]);
-      rsum += Ml[rr][t + TH] - (Lc)0.5 * (Lc)ds[rr][t];        // Rloc at node column i
+      rsum += Pn[rr][t];                                        // Rloc at node column i
       A v = sb;
       acc_add_local(v, rsum);
       sv[rr] = (St)to_store(v);
