@@ -231,10 +231,10 @@ int cg_set_tile_shape(cg_ctx* ctx, int N, int precision, int64_t batch_pixels, i
 int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* cache_path);
 
 /* Timing of one pipeline stage inside cg_step_series (profiling aid).
- * cg_profile_stage selects the stage ("raster_count", "raster_scan",
- * "raster_emit", "raster_fill", "density", "sat_reduce", "sat_carry1",
- * "sat_carry2", "sat_final", "map_points", "areas", "err"; NULL or "" to
- * stop) and resets the totals.  While selected, the launch of that kernel
+ * cg_profile_stage selects the stage ("raster_emit", "raster_fill",
+ * "density", "sat_reduce", "sat_carry1", "sat_carry2", "sat_final",
+ * "map_points", "areas", "err"; NULL or "" to stop) and resets the
+ * totals.  While selected, the launch of that kernel
  * in one of every `every` iterations is bracketed by HIP events recorded
  * on the launch stream, and cg_profile_read returns the summed
  * milliseconds and the number of launches timed so far.  Events are only

@@ -142,7 +142,7 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   for (const Spec& s : specs) P.il = P.il && !s.S && !s.T;
   // scratch layout
   struct Own {
-    int64_t rowcnt = -1, rowoff = -1, xing = -1, labels = -1, counts = -1, lut = -1, S = -1, T = -1,
+    int64_t rowcnt = -1, xing = -1, labels = -1, counts = -1, lut = -1, S = -1, T = -1,
             HA = -1, HB = -1, agg = -1, carry = -1, areas = -1;
   };
   std::vector<Own> owns(n);
@@ -197,10 +197,8 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     // scratch offsets relative to the instance base (-1: caller buffer or unused)
     Own& ow = owns[k];
     if (nd.raster) {
-      I.xing_cap = std::max<int64_t>(4 * (int64_t)I.n_edges + 64 * (int64_t)N, 4096);
       ow.rowcnt = take(sizeof(uint32_t) * N);
-      ow.rowoff = take(sizeof(uint32_t) * (N + 1));
-      ow.xing = take(sizeof(uint64_t) * I.xing_cap);
+      ow.xing = take(sizeof(uint64_t) * (size_t)N * cgk::kFillXing);   // a bucket per row
     }
     if ((nd.raster || nd.sat) && !dense && !s.labels) ow.labels = take(sizeof(uint16_t) * (size_t)N * N);
     if (nd.raster && !s.counts) ow.counts = take(sizeof(int64_t) * (R + 1));
@@ -238,7 +236,6 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     char* b = scratch + base[k];
     auto at = [&](int64_t off) -> char* { return off >= 0 ? b + off : nullptr; };
     I.row_cnt = (uint32_t*)at(ow.rowcnt);
-    I.row_off = (uint32_t*)at(ow.rowoff);
     I.xing = (uint64_t*)at(ow.xing);
     if (ow.labels >= 0) I.labels = (uint16_t*)at(ow.labels);
     if (ow.counts >= 0) I.counts = (int64_t*)at(ow.counts);
@@ -258,8 +255,10 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   for (int k = 0; k < n; ++k) {
     const Inst& I = P.inst[k];
     SatLayout L = cgk::sat_layout(I.N, tw, th);
+    // every instance gets an edge block: its first one clears the totals
+    // the rasteriser's fill accumulates
     const int64_t cnt[8] = {
-        (I.n_edges + 255) / 256,
+        std::max<int64_t>(1, (I.n_edges + 255) / 256),
         (I.N + kFillRows - 1) / kFillRows,
         (int64_t)L.ntx * L.nty,
         (L.NY + L.nty + 1 + 255) / 256,
@@ -750,7 +749,7 @@ int cg_autotune(cg_ctx* c, int N, int precision, int32_t batch, const char* cach
 }
 
 static const char* kStageNames[cgk::ST_COUNT] = {
-    "raster_count", "raster_scan", "raster_emit", "raster_fill", "density", "sat_reduce",
+    "raster_emit", "raster_fill", "density", "sat_reduce",
     "sat_carry1", "sat_carry2", "sat_final", "map_points", "areas", "err"};
 
 int cg_profile_stage(cg_ctx* c, const char* stage, int32_t every) {

@@ -15,14 +15,14 @@ namespace cgk {
 
 constexpr int kSub = 256;          // fixed-point subdivisions per pixel (rasteriser)
 constexpr int kLutLds = 1024;      // LUT entries kept in LDS by the scan / fill kernels
-constexpr int kRowXingMax = 1024;  // crossings one row may hold in LDS
+constexpr int kFillXing = 256;     // crossings one row may hold (its bucket; LDS of the fill kernel)
 constexpr int kSetCap = 8;         // simultaneous claims tracked per pixel run
 constexpr int kFillRows = 4;       // label rows per fill block (one per wavefront)
 constexpr int kCarryRows = 8;      // tile rows one carry thread sums
 
 // Pipeline stages of one iteration (for per-stage timing hooks).
 enum Stage {
-  ST_RASTER_COUNT = 0, ST_RASTER_SCAN, ST_RASTER_EMIT, ST_RASTER_FILL, ST_DENSITY,
+  ST_RASTER_EMIT = 0, ST_RASTER_FILL, ST_DENSITY,
   ST_SAT_REDUCE, ST_SAT_CARRY1, ST_SAT_CARRY2, ST_SAT_FINAL, ST_MAP, ST_AREAS, ST_ERR, ST_COUNT
 };
 // Called on the host right before (after = 0) and after (after = 1) a
@@ -38,7 +38,6 @@ struct IterState {
   int32_t flags;      // CG_FLAG_*
   int32_t evaluated;  // the error of the starting positions is known
   int64_t contested;  // contested pixels in the latest label map
-  int64_t xings;      // row crossings in the latest label map
   double xi, eps, best_xi;
   double d0, C;       // density parameters of the latest iteration
   double xi0;         // max error of the plain (not warm-started) start
@@ -68,7 +67,7 @@ struct InstT {
   int32_t tw, th, ntx, nty;           // integral-image tiling
   int32_t area_source, patience, max_iters, fixed_iters;
   float shape, tol;
-  int64_t pitch, xing_cap;
+  int64_t pitch;
   // topology
   typename PP::template p<const int4> edges;                  // (v0, v1, region A, region B)
   typename PP::template p<const int32_t> ring_off;
@@ -83,9 +82,8 @@ struct InstT {
   typename PP::template p<const float> init_field;            // warm-start displacement [G][G][2] at pixel centres, or null
   int64_t init_G;
   typename PP::template p<const float> values;                // [R]
-  typename PP::template p<uint32_t> row_cnt;                  // [N]
-  typename PP::template p<uint32_t> row_off;                  // [N+1]
-  typename PP::template p<uint64_t> xing;                     // [xing_cap]
+  typename PP::template p<uint32_t> row_cnt;                  // [N] crossings per row (bucket fill)
+  typename PP::template p<uint64_t> xing;                     // [N][kFillXing] crossing buckets
   typename PP::template p<uint16_t> labels;                   // [N][N]
   typename PP::template p<int64_t> counts;                    // [R+1]
   typename PP::template p<float> lut;                         // [n_lut]

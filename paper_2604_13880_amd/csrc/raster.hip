@@ -13,16 +13,15 @@
 // map has folded) takes the highest id and is counted as contested.
 //
 // Kernels (one launch each per iteration, covering every instance):
-//   k_raster_count  one thread per edge: crossings per row (int atomics)
-//   k_raster_scan   one block per instance: row offsets, counter resets
 //   k_raster_emit   one thread per edge: (p0, region A, region B) records
+//                   appended to the bucket of every row the edge crosses
+//                   (kFillXing records per row; an integer atomic per
+//                   crossing picks the slot)
 //   k_raster_fill   one wavefront per row: sort by p0, walk, write labels,
 //                   per-region counts aggregated in LDS
 #include "cg_dev.h"
 
 namespace cgk {
-
-constexpr int kFillXing = 256;    // crossings per row held in LDS
 
 __device__ __forceinline__ int snapc(float v, float scale) { return (int)rintf(v * scale); }
 
@@ -33,71 +32,14 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
   q1 = min((hi - kSub / 2 + kSub - 1) >> 8, N);
 }
 
-__global__ __launch_bounds__(256) void k_raster_count(Batch B) {
-  const int k = find_inst(B.off_edges, B.n, blockIdx.x);
-  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
-  const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
-  if (e >= I.n_edges) return;
-  const int4 E = ld4(I.edges + e);
-  const float scale = (float)(kSub * I.N);
-  const int ya = snapc(ld2(I.xy + E.x).y, scale), yb = snapc(ld2(I.xy + E.y).y, scale);
-  int q0, q1;
-  crossed_rows(ya, yb, I.N, q0, q1);
-  for (int q = q0; q < q1; ++q) g_atomic_add(&I.row_cnt[q], 1u);
-}
-
-__global__ __launch_bounds__(1024) void k_raster_scan(Batch B) {
-  const int k = find_inst(B.off_inst, B.n, blockIdx.x);
-  const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
-  __shared__ uint32_t wsum[16];
-  const int N = I.N, t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int per = (N + 1023) / 1024;
-  const int base = t * per;
-  uint32_t loc[8];
-  uint32_t sum = 0;
-  for (int c = 0; c < per; ++c) {
-    const int q = base + c;
-    const uint32_t v = q < N ? I.row_cnt[q] : 0u;
-    loc[c] = v;
-    sum += v;
-  }
-  // block exclusive scan of the per-thread sums
-  uint32_t x = sum;
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  uint32_t wpre = 0, total = 0;
-  for (int i = 0; i < 16; ++i) {
-    if (i < w) wpre += wsum[i];
-    total += wsum[i];
-  }
-  uint32_t run = wpre + x - sum;
-  for (int c = 0; c < per; ++c) {
-    const int q = base + c;
-    if (q < N) {
-      I.row_off[q] = run;
-      I.row_cnt[q] = 0u;
-    }
-    run += loc[c];
-  }
-  if (t == 0) {
-    I.row_off[N] = total;
-    I.st->xings = total;
-    I.st->contested = 0;
-    if ((int64_t)total > I.xing_cap) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
-  }
-  for (int v = t; v <= I.R; v += 1024) I.counts[v] = 0;
-}
-
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   const int k = find_inst(B.off_edges, B.n, blockIdx.x);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
+  if (blockIdx.x == B.off_edges[k]) {   // the instance's first block: clear the fill's totals
+    for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
+    if (threadIdx.x == 0) I.st->contested = 0;
+  }
   const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
   const int4 E = ld4(I.edges + e);
@@ -122,8 +64,8 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
     const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
     int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
     if (p0 > N) p0 = N;
-    const uint32_t slot = I.row_off[q] + g_atomic_add(&I.row_cnt[q], 1u);
-    if ((int64_t)slot < I.xing_cap) I.xing[slot] = (uint64_t)p0 | regs;
+    const uint32_t slot = g_atomic_add(&I.row_cnt[q], 1u);   // a full bucket is the fill's overflow
+    if (slot < (uint32_t)kFillXing) I.xing[(int64_t)q * kFillXing + slot] = (uint64_t)p0 | regs;
   }
 }
 
@@ -250,8 +192,8 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
     bool bad = false;
     if (row_ok) {
       cnt = I.row_cnt[q];
-      off = I.row_off[q];
-      if (cnt > (uint32_t)kFillXing || (int64_t)off + cnt > I.xing_cap) bad = true;
+      off = (uint32_t)q * (uint32_t)kFillXing;
+      if (cnt > (uint32_t)kFillXing) bad = true;
       if (bad) cnt = 0;
       for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
     }
@@ -502,14 +444,6 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
 void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u) {
   auto hk = [&](int st, int after) { if (h) h(st, after, u); };
-  if (edge_blocks > 0) {
-    hk(ST_RASTER_COUNT, 0);
-    hipLaunchKernelGGL(k_raster_count, dim3(edge_blocks), dim3(256), 0, s, B);
-    hk(ST_RASTER_COUNT, 1);
-  }
-  hk(ST_RASTER_SCAN, 0);
-  hipLaunchKernelGGL(k_raster_scan, dim3(B.n), dim3(1024), 0, s, B);
-  hk(ST_RASTER_SCAN, 1);
   if (edge_blocks > 0) {
     hk(ST_RASTER_EMIT, 0);
     hipLaunchKernelGGL(k_raster_emit, dim3(edge_blocks), dim3(256), 0, s, B);
