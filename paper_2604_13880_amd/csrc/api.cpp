@@ -286,6 +286,9 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   B.inst = (const Inst*)desc;
   B.n = n;
   B.skip_done = 1;
+  B.max_n = 0;
+  for (int k = 0; k < n; ++k) B.max_n = std::max(B.max_n, (int32_t)P.inst[k].N);
+  B.pad0 = 0;
   B.off_edges = doff + 0 * (n + 1);
   B.off_rows = doff + 1 * (n + 1);
   B.off_tiles = doff + 2 * (n + 1);

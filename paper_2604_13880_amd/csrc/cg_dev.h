@@ -107,6 +107,8 @@ struct Batch {
   const Inst* inst;
   int32_t n;
   int32_t skip_done;                  // 1: instances whose state says done are skipped
+  int32_t max_n;                      // largest texture of the batch
+  int32_t pad0;
   const int64_t* off_edges;
   const int64_t* off_rows;
   const int64_t* off_tiles;

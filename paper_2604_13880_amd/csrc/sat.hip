@@ -114,6 +114,7 @@ struct Stager {
 };
 
 constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of the tile)
+constexpr int kPrefLds = 1024;    // tile-row prefix totals the carry pass keeps in LDS
 constexpr int kReduce_Rows = 8;   // rows per sub-band of the reduce pass (every thread loads)
 
 // Row prefix sums of one sub-band: M[rr][c] = base + (L(c) - L(c0)) + d(c)/2
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
 // Mass of tile row ty on the anti-diagonal side u (tiles fully below u give
 // their totals through the tile-row prefix, at most two tiles are cut).
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t u) {
+__device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const Cy* pref, const SatLayout& L, int ty, int64_t u) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(u - y0 - TW - TH + 2, TW);
@@ -481,14 +482,14 @@ __device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const SatLayout& L, in
   int64_t khi = floordiv(u - y0, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
   const int64_t base = L.cdfA + (int64_t)ty * L.ntx * D;
-  Cy s = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
+  Cy s = pref ? pref[(int64_t)ty * (L.ntx + 1) + klo] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
   if (klo <= khi) s += agg[base + klo * D + (u - klo * TW - y0)];
   if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (u - (klo + 1) * TW - y0)];
   return s;
 }
 
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t v) {
+__device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const Cy* pref, const SatLayout& L, int ty, int64_t v) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(v + y0 - TW + 1, TW);
@@ -496,7 +497,7 @@ __device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const SatLayout& L, in
   int64_t khi = floordiv(v + y0 + TH - 1, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
   const int64_t base = L.cdfB + (int64_t)ty * L.ntx * D;
-  Cy s = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
+  Cy s = pref ? pref[(int64_t)ty * (L.ntx + 1) + klo] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
   if (klo <= khi) s += agg[base + klo * D + (v - klo * TW + y0 + TH - 1)];
   if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (v - (klo + 1) * TW + y0 + TH - 1)];
   return s;
@@ -506,7 +507,7 @@ __device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const SatLayout& L, in
 // anti-diagonal u for TA, diagonal v for TB) an exclusive scan over the tile
 // rows of the band values.  A block holds IPB indices x CH chunks of
 // kCarryRows tile rows; chunk sums are joined by an LDS scan.
-template <int P, int TW, int TH>
+template <int P, int TW, int TH, bool PREF_LDS>
 __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
@@ -515,7 +516,23 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   if (inst_done(B, I)) return;
   __shared__ Cy part[256];
   __shared__ Cy partC[256];
+  __shared__ Cy pref_s[PREF_LDS ? kPrefLds : 1];
   const SatLayout L = sat_layout(I.N, TW, TH);
+  if (PREF_LDS) {
+    // tile-row prefix totals, one thread per tile row (the order of the
+    // row-carry pass): nty <= 256 and nty (ntx + 1) <= kPrefLds here
+    g_ptr<const Cy> ag = (g_ptr<const Cy>)I.agg;
+    for (int ty = threadIdx.x; ty < L.nty; ty += 256) {
+      Cy run = 0;
+      for (int tx = 0; tx < L.ntx; ++tx) {
+        pref_s[ty * (L.ntx + 1) + tx] = run;
+        run += ag[L.tileTot + (int64_t)ty * L.ntx + tx];
+      }
+      pref_s[ty * (L.ntx + 1) + L.ntx] = run;
+    }
+    __syncthreads();
+  }
+  const Cy* pref = PREF_LDS ? pref_s : nullptr;
   const int N = I.N, nty = L.nty;
   const int CH = L.carry_ch, IPB = 256 / CH;
   const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
@@ -536,13 +553,13 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
         const int i = (int)idx;
         int tx = i / TW;
         if (tx > L.ntx - 1) tx = L.ntx - 1;
-        v = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx] +
+        v = (PREF_LDS ? pref[ty * (L.ntx + 1) + tx] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx]) +
             agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + (i - tx * TW)];
       } else if (seg == 1) {
-        v = band_a<TW, TH, Cy>(agg, L, ty, idx - nS - 1);
+        v = band_a<TW, TH, Cy>(agg, pref, L, ty, idx - nS - 1);
       } else if (seg == 2) {
-        v = band_b<TW, TH, Cy>(agg, L, ty, idx - nS - L.LA - L.NY);
-        w = agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx];
+        v = band_b<TW, TH, Cy>(agg, pref, L, ty, idx - nS - L.LA - L.NY);
+        w = PREF_LDS ? pref[ty * (L.ntx + 1) + L.ntx] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx];
       }
     }
     band[d] = v;
@@ -640,7 +657,18 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     from_carry(ca_s[sl], carry[L.TAc + (int64_t)ty * L.LA + x0 + y0 + sl]);
     from_carry(cb_s[sl], carry[L.TBc + (int64_t)ty * L.LB + (x0 - y0 - TH + L.NY) + sl]);
   }
-  for (int r = t; r < TH; r += TW) from_carry(rc_s[r], agg[L.RC + (int64_t)tx * L.NY + y0 + r]);
+  for (int r = t; r < TH; r += TW) {   // row carries: the rows' totals in the tile columns to the left
+    Cy run = 0;                          // (loads issued 8 at a time, summed in column order)
+    for (int c0 = 0; c0 < tx; c0 += 8) {
+      Cy v[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = c0 + c < tx ? agg[L.rowTot + (int64_t)(c0 + c) * L.NY + y0 + r] : (Cy)0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < tx) run += v[c];
+    }
+    from_carry(rc_s[r], run);
+  }
   typedef typename Pair<St>::type St2;
   g_ptr<St> S = (g_ptr<St>)I.S;
   g_ptr<St> T = (g_ptr<St>)I.T;
@@ -789,11 +817,18 @@ static void launch_sat_t(const Batch& B, bool dense, bool il, int64_t tiles, int
   if (dense) hipLaunchKernelGGL((k_sat_reduce<P, TW, TH, true>), dim3(tiles), dim3(TW), 0, s, B);
   else hipLaunchKernelGGL((k_sat_reduce<P, TW, TH, false>), dim3(tiles), dim3(TW), 0, s, B);
   hk(ST_SAT_REDUCE, 1);
-  hk(ST_SAT_CARRY1, 0);
-  hipLaunchKernelGGL((k_sat_carry1<P, TW, TH>), dim3(c1), dim3(256), 0, s, B);
-  hk(ST_SAT_CARRY1, 1);
+  // the carry pass builds the tile-row prefix totals in LDS when every
+  // instance's table fits; otherwise the row-carry pass writes them
+  const SatLayout Lm = sat_layout(B.max_n, TW, TH);
+  const bool pref_lds = Lm.nty <= 256 && (int64_t)Lm.nty * (Lm.ntx + 1) <= kPrefLds;
+  if (!pref_lds) {
+    hk(ST_SAT_CARRY1, 0);
+    hipLaunchKernelGGL((k_sat_carry1<P, TW, TH>), dim3(c1), dim3(256), 0, s, B);
+    hk(ST_SAT_CARRY1, 1);
+  }
   hk(ST_SAT_CARRY2, 0);
-  hipLaunchKernelGGL((k_sat_carry2<P, TW, TH>), dim3(c2), dim3(256), 0, s, B);
+  if (pref_lds) hipLaunchKernelGGL((k_sat_carry2<P, TW, TH, true>), dim3(c2), dim3(256), 0, s, B);
+  else hipLaunchKernelGGL((k_sat_carry2<P, TW, TH, false>), dim3(c2), dim3(256), 0, s, B);
   hk(ST_SAT_CARRY2, 1);
   hk(ST_SAT_FINAL, 0);
   if (dense) hipLaunchKernelGGL((k_sat_final<P, TW, TH, true, false>), dim3(tiles), dim3(TW), 0, s, B);
