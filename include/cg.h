@@ -234,7 +234,10 @@ int cg_autotune(cg_ctx* ctx, int N, int precision, int32_t batch, const char* ca
  * cg_profile_stage selects the stage ("raster_emit", "raster_fill",
  * "density", "sat_reduce", "sat_carry1", "sat_carry2", "sat_final",
  * "map_points", "areas", "err"; NULL or "" to stop) and resets the
- * totals.  While selected, the launch of that kernel
+ * totals.  "density" and "sat_carry1" are separate launches only for
+ * batches where folding them into the integral-image passes does not pay
+ * (large LUT work, tables too large for LDS); otherwise they report no
+ * launches.  While selected, the launch of that kernel
  * in one of every `every` iterations is bracketed by HIP events recorded
  * on the launch stream, and cg_profile_read returns the summed
  * milliseconds and the number of launches timed so far.  Events are only

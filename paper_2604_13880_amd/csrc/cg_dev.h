@@ -108,7 +108,7 @@ struct Batch {
   int32_t n;
   int32_t skip_done;                  // 1: instances whose state says done are skipped
   int32_t max_n;                      // largest texture of the batch
-  int32_t pad0;
+  int32_t make_lut;                   // 1: the integral-image reduce pass builds the density LUT (Step 3)
   const int64_t* off_edges;
   const int64_t* off_rows;
   const int64_t* off_tiles;

@@ -50,6 +50,7 @@ struct cg_ctx {
   int prof_stage = -1;
   int prof_every = 1;        // time one launch in every prof_every iterations
   std::vector<hipEvent_t> prof_ev;
+  std::vector<char> prof_rec;   // the event pair of an iteration was recorded in this launch sequence
   int prof_k = 0;            // iterations recorded per graph replay
   double prof_ms = 0.0;
   int64_t prof_launches = 0;

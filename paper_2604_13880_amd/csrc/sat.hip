@@ -338,6 +338,68 @@ __device__ __forceinline__ void acc_add_local<double, double>(double& a, double 
 // s = (p - x0) - (q - y0) + TH - 1.  The mass of the tile below an
 // anti-diagonal slot c (pixels bisected by it count half) is then
 // sum_{s<c} h_a(s) + h_a(c)/2, and likewise for the diagonals.
+// Step 3 inside the reduce pass: every block builds the instance's density
+// LUT in LDS from the pixel counts (or polygon areas) and the values, in
+// one fixed order, so all blocks hold the same table; the instance's first
+// block also publishes it (and d0, C) for the writer.  d0 = sum s / sum o
+// over regions with o > 0, background density shape * d0, LUT scaled so
+// the texture mass is N^2.
+template <int NT>
+__device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool publish) {
+  constexpr int NW = NT / 64;
+  __shared__ double part[3][NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, R = I.R;
+  const double NN = (double)I.N * (double)I.N;
+  const bool poly = I.area_source == CG_AREA_POLYGON;
+  double ss = 0.0, so = 0.0, sc = 0.0;
+  for (int v = 1 + t; v <= R; v += NT) {
+    const double cnt = (double)I.counts[v];
+    const double o = poly ? I.areas[v] * NN : cnt;
+    if (o > 0.0) {
+      const double s = (double)I.values[v - 1];
+      ss += s;
+      sc += s / o * cnt;
+    }
+    so += o;
+  }
+  ss = wave_inclusive_scan_dpp(ss);   // lane 63: the wavefront's sum
+  so = wave_inclusive_scan_dpp(so);
+  sc = wave_inclusive_scan_dpp(sc);
+  if (lane == 63) {
+    part[0][w] = ss;
+    part[1][w] = so;
+    part[2][w] = sc;
+  }
+  __syncthreads();
+  ss = so = sc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    ss += part[0][i];
+    so += part[1][i];
+    sc += part[2][i];
+  }
+  const double d0 = so > 0.0 ? ss / so : 1.0;
+  const double bdv = (double)I.shape * d0;
+  const double cm = sc + bdv * (double)I.counts[0];
+  const double kappa = cm > 0.0 ? NN / cm : 1.0;
+  g_ptr<float> lut = (g_ptr<float>)I.lut;
+  for (int v = 1 + t; v <= R; v += NT) {
+    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+    const float x = o > 0.0 ? (float)(kappa * ((double)I.values[v - 1] / o)) : 0.f;
+    lut_s[v] = x;
+    if (publish) lut[v] = x;
+  }
+  if (t == 0) {
+    const float x0 = (float)(kappa * bdv);
+    lut_s[0] = x0;
+    if (publish) {
+      lut[0] = x0;
+      I.st->d0 = d0;
+      I.st->C = cm;
+    }
+  }
+}
+
 template <int P, int TW, int TH, bool DENSE>
 __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   typedef typename PT<P>::acc A;
@@ -360,7 +422,8 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
-  if (lut_lds)
+  if (!DENSE && B.make_lut) density_lut<TW>(I, lut_s, tile == 0);   // R + 1 <= kLutLds (host)
+  else if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
   typedef typename LocalT<P>::type Lc;
   Lc col = 0, ha0 = 0, ha1 = 0, hb0 = 0, hb1 = 0;
