@@ -98,6 +98,15 @@ int cg_net_load(cg_net* net, const char* path);
 int cg_log_density(cg_ctx* ctx, int N, const uint16_t* labels, const int64_t* counts, const float* values,
                    int32_t n_regions, float shape, float* out, void* stream);
 
+/* Log-density textures of n maps in one call (one rasterisation plan for
+ * all): for map k, the texture of cg_log_density from the labels and counts
+ * cg_rasterize gives for maps[k] at positions xy[k].  maps, xy and values
+ * are HOST arrays of n pointers; xy[k] device float [n_vertices_k][2],
+ * values[k] device float [R_k] (1 <= R_k <= 65535), out device float
+ * [n][N][N].  The learned warm start's first input channel for a batch. */
+int cg_log_density_maps(cg_ctx* ctx, int32_t n, const cg_map* const* maps, const float* const* xy, int N,
+                        const float* const* values, float shape, float* out, void* stream);
+
 /* Tracer grid of G x G pixel centres: with final == NULL, out[j][i] =
  * ((i + 1/2)/G, (j + 1/2)/G); otherwise out[j][i] = final[j][i] - that
  * centre (the displacement of tracers moved along by cg_step_series).

@@ -83,6 +83,7 @@ def lib():
             "cg_profile_stage": (C.c_int, [vp, C.c_char_p, i32]),
             "cg_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
             "cg_log_density": (C.c_int, [vp, C.c_int, vp, vp, vp, i32, C.c_float, vp, vp]),
+            "cg_log_density_maps": (C.c_int, [vp, i32, vp, vp, C.c_int, vp, C.c_float, vp, vp]),
             "cg_tracer_field": (C.c_int, [vp, i32, vp, vp, vp]),
             "cg_field_pool": (C.c_int, [vp, i32, vp, i32, vp, vp]),
             "cg_net_create": (C.c_int, [vp, C.POINTER(CgNetConfig), C.POINTER(vp)]),
@@ -110,7 +111,7 @@ def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
             "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
             "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
-            "cg_profile_read", "cg_log_density", "cg_tracer_field", "cg_field_pool", "cg_net_create", "cg_net_destroy",
+            "cg_profile_read", "cg_log_density", "cg_log_density_maps", "cg_tracer_field", "cg_field_pool", "cg_net_create", "cg_net_destroy",
             "cg_net_n_params", "cg_net_get_params", "cg_net_set_params", "cg_net_get_grads", "cg_net_zero_grads",
             "cg_net_forward", "cg_net_backward", "cg_net_adam_step", "cg_net_save", "cg_net_load"]
 
@@ -284,6 +285,20 @@ class Context:
         rc = lib().cg_log_density(self.handle, N, _ptr(labels.contiguous()), _ptr(counts), _ptr(vals),
                                   int(vals.numel()), float(shape), _ptr(out), _stream())
         self._check(rc, "cg_log_density")
+        return out
+
+    def log_density_maps(self, maps, xys, N: int, values, shape: float = 1.0):
+        """log(d / mean d) textures [n][N][N] of several maps in one call
+        (device positions xys[k] [n_k][2] and values[k] [R_k])."""
+        n = len(maps)
+        xs = [_dev(x, torch.float32, (-1, 2)) for x in xys]
+        vs = [_dev(v, torch.float32) for v in values]
+        out = torch.empty((n, N, N), dtype=torch.float32, device="cuda")
+        mp = (C.c_void_p * n)(*[m.handle for m in maps])
+        xp = (C.c_void_p * n)(*[_ptr(x) for x in xs])
+        vp_ = (C.c_void_p * n)(*[_ptr(v) for v in vs])
+        rc = lib().cg_log_density_maps(self.handle, n, mp, xp, int(N), vp_, float(shape), _ptr(out), _stream())
+        self._check(rc, "cg_log_density_maps")
         return out
 
     def tracer_grid(self, G: int):

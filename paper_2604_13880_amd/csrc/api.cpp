@@ -816,6 +816,40 @@ int cg_log_density(cg_ctx* c, int N, const uint16_t* labels, const int64_t* coun
   return check_launch(c);
 }
 
+int cg_log_density_maps(cg_ctx* c, int32_t n, const cg_map* const* maps, const float* const* xy, int N,
+                        const float* const* values, float shape, float* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  if (n < 1 || !maps || !xy || !values || !out) return fail(c, CG_EINVAL, "cg_log_density_maps: null argument");
+  if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_log_density_maps: N must be a power of two in [16, 8192]");
+  if (!(shape >= 0)) return fail(c, CG_EINVAL, "cg_log_density_maps: need shape >= 0");
+  int32_t maxR = 0;
+  std::vector<Spec> specs(n);
+  for (int k = 0; k < n; ++k) {
+    if (!maps[k] || !xy[k] || !values[k]) return fail(c, CG_EINVAL, "cg_log_density_maps: null map, positions or values");
+    if (maps[k]->R < 1 || maps[k]->R > 65535) return fail(c, CG_EINVAL, "cg_log_density_maps: need 1 <= R <= 65535");
+    maxR = std::max(maxR, maps[k]->R);
+    specs[k].map = maps[k];
+    specs[k].N = N;
+    specs[k].xy = (float2*)xy[k];
+  }
+  (void)hipSetDevice(c->device);
+  hipStream_t st = pick_stream(c, stream);
+  Needs nd;
+  nd.raster = true;
+  Plan P;
+  int rc = build_plan(c, specs, CG_F32, 64, 16, false, nd, st, P, "logd");
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  cgk::launch_init(P.B, P.pt_blocks, st);
+  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+  char* lut = nullptr;
+  if ((rc = get_buf(c, "log_lut", sizeof(float) * (size_t)(maxR + 1), st, &lut))) return rc;
+  for (int k = 0; k < n; ++k)   // stream order: each launch has the LUT scratch to itself
+    cgk::launch_log_density(P.inst[k].labels, P.inst[k].counts, values[k], maps[k]->R, N, shape, (float*)lut,
+                            out + (size_t)k * N * N, st);
+  return check_launch(c);
+}
+
 int cg_tracer_field(cg_ctx* c, int32_t G, const float* final_xy, float* out, void* stream) {
   if (!c) return CG_EINVAL;
   if (!out || G < 1 || G > 65536) return fail(c, CG_EINVAL, "cg_tracer_field: need out and 1 <= G <= 65536");

@@ -33,11 +33,14 @@ if ROOT not in sys.path:
 
 TRAIN_SEED0 = 5_000_000     # training maps: seeds TRAIN_SEED0 + k
 TEST_SEED0 = 6_000_000      # held-out maps
-N_TEX = 512
+N_TEX = 512              # texture of the cartograms
+N_NET = 256              # grid of the net's input and output (pixel centres of a 256^2 grid)
 FEATURE_ITERS = 1
-WARM_POOL = 4            # the predicted field is box-averaged over 4 x 4 pixels before use
+WARM_POOL = 4            # the predicted field is box-averaged over 4 x 4 cells (a 64^2 field) before use
+PREDICT_BATCH = 32
+WEIGHTS_NAME = "warm_start_256.bin"
 RESIDUAL_GAIN = 2.4      # median ratio of the final to the first-iteration displacement on training maps
-NET_CFG = dict(base_channels=32, levels=4, height=N_TEX, width=N_TEX, out_scale=0.1, in_channels=3,
+NET_CFG = dict(base_channels=32, levels=4, height=N_NET, width=N_NET, out_scale=0.1, in_channels=3,
                residual_gain=RESIDUAL_GAIN)
 
 
@@ -60,14 +63,23 @@ def make_maps(seeds, rmin=50, rmax=150, per_region=250, sigma=1.0, workers=16):
         return pool.map(_make_map, args, chunksize=max(1, len(args) // (4 * workers)))
 
 
-def net_inputs(ctx, maps, N=N_TEX, shape=1.0, gmaps=None):
-    """log-density textures [n][N][N] (device float32) of the original maps."""
+def net_inputs(ctx, maps, N=N_NET, shape=1.0, gmaps=None, batch=64):
+    """log-density textures [n][N][N] (device float32) of the original maps,
+    `batch` maps per library call (positions and values uploaded at once)."""
     import torch
     out = torch.empty((len(maps), N, N), dtype=torch.float32, device="cuda")
-    for k, (m, s) in enumerate(maps):
-        gm = ctx.map_from(m) if gmaps is None else gmaps[k]
-        lab, cnt, _ = ctx.rasterize(gm, m.xy32(), N)
-        out[k] = ctx.log_density(lab, cnt, torch.from_numpy(s).cuda(), shape=shape)
+    for b0 in range(0, len(maps), batch):
+        part = maps[b0:b0 + batch]
+        gm = [ctx.map_from(m) for m, s in part] if gmaps is None else gmaps[b0:b0 + batch]
+        xy = torch.from_numpy(np.concatenate([m.xy32() for m, s in part])).cuda()
+        vals = torch.from_numpy(np.concatenate([s for m, s in part]).astype(np.float32)).cuda()
+        xys, vs, o, r = [], [], 0, 0
+        for m, s in part:
+            xys.append(xy[o:o + m.n_vertices])
+            vs.append(vals[r:r + len(s)])
+            o += m.n_vertices
+            r += len(s)
+        out[b0:b0 + len(part)] = ctx.log_density_maps(gm, xys, N, vs, shape=shape)
     return out
 
 
@@ -92,14 +104,16 @@ def plain_runs(ctx, maps, N=N_TEX, G=N_TEX, batch=32, graph_iters=8, gmaps=None,
     return fields, stats
 
 
-def features(ctx, maps, N=N_TEX, gmaps=None, **kw):
-    """Net input [n][N][N][3]: log-density and the tracer displacement after
-    FEATURE_ITERS plain iterations (same stopping parameters otherwise)."""
+def features(ctx, maps, N=N_TEX, G=N_NET, gmaps=None, **kw):
+    """Net input [n][G][G][3]: log-density on the G x G grid and the
+    displacement of a G x G tracer grid after FEATURE_ITERS plain
+    iterations at texture N (same stopping parameters otherwise)."""
     import torch
     kw = dict(kw)
     kw.pop("max_iters", None)
-    X0 = net_inputs(ctx, maps, N, gmaps=gmaps)
-    D, _ = plain_runs(ctx, maps, N, N, gmaps=gmaps, fixed_iters=FEATURE_ITERS, **kw)
+    X0 = net_inputs(ctx, maps, G, gmaps=gmaps)
+    # a few iterations: eager launches (a captured graph would cost more than it saves)
+    D, _ = plain_runs(ctx, maps, N, G, gmaps=gmaps, graph_iters=-FEATURE_ITERS, fixed_iters=FEATURE_ITERS, **kw)
     return torch.cat([X0[..., None], D], dim=-1).contiguous()
 
 
@@ -137,7 +151,7 @@ def train(net, X, Y, epochs=4, batch=16, lr=1e-3, lr_end=1e-4, seed=0, log=print
     return hist
 
 
-def predict(net, X, batch=8, pool=1):
+def predict(net, X, batch=PREDICT_BATCH, pool=1):
     """Predicted fields [n][G/pool][G/pool][2]."""
     import torch
     G = X.shape[1] // pool
@@ -178,6 +192,11 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
     import torch
     gmaps = [ctx.map_from(m) for m, s in maps]
     n = len(maps)
+    # untimed first calls of both paths (buffer allocation, code loading)
+    k0 = min(n, 4)
+    run_batched(ctx, gmaps[:k0], maps[:k0], None, N, batch, graph_iters, **kw)
+    Fw = predict(net, features(ctx, maps[:k0], N, gmaps=gmaps[:k0], **kw), pool=WARM_POOL)
+    run_batched(ctx, gmaps[:k0], maps[:k0], Fw, N, batch, graph_iters, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain = run_batched(ctx, gmaps, maps, None, N, batch, graph_iters, **kw)
@@ -195,7 +214,10 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
     kq = {k: v for k, v in kw.items() if k != "tol"}
     eq_w = dict(iters=[], xi=[], status=[])
     eq_p = dict(iters=[], xi=[], status=[])
+    eq_ms = {}
     for side, fields, acc in (("warm", F, eq_w), ("plain", None, eq_p)):
+        torch.cuda.synchronize()
+        te = time.perf_counter()
         for b0 in range(0, n, batch):
             descs = []
             for k in range(b0, min(b0 + batch, n)):
@@ -208,6 +230,8 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
                 acc["iters"].append(int(r["iters"][0]))
                 acc["xi"].append(float(r["xi"][0]))
                 acc["status"].append(int(r["status"][0]))
+        torch.cuda.synchronize()
+        eq_ms[side] = (time.perf_counter() - te) * 1e3 / n
     eqw = {k: np.asarray(v) for k, v in eq_w.items()}
     eqp = {k: np.asarray(v) for k, v in eq_p.items()}
     reached_w = eqw["status"] == 0
@@ -224,6 +248,8 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
                    maps_reaching_plain_quality_warm=int(reached_w.sum()),
                    maps_reaching_plain_quality_plain=int(reached_p.sum()),
                    warm_iters_mean=float(eqw["iters"].mean()), plain_iters_mean=float(eqp["iters"].mean()),
+                   plain_ms_per_cartogram=eq_ms["plain"],
+                   warm_ms_per_cartogram=eq_ms["warm"] + (t2 - t1) * 1e3 / n,   # with the net's inputs and forward
                    iters_saved_mean_where_both_reach=float((eqp["iters"] - eqw["iters"])[reached_w & reached_p].mean())
                    if (reached_w & reached_p).any() else None),
                warm_field_pool=WARM_POOL)
@@ -242,8 +268,8 @@ def main(argv=None):
     from paper_2604_13880_amd import binding as B
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train", "eval"])
-    ap.add_argument("--out", default=os.path.join(HERE, "weights", "warm_start_512.bin"))
-    ap.add_argument("--weights", default=os.path.join(HERE, "weights", "warm_start_512.bin"))
+    ap.add_argument("--out", default=os.path.join(HERE, "weights", WEIGHTS_NAME))
+    ap.add_argument("--weights", default=os.path.join(HERE, "weights", WEIGHTS_NAME))
     ap.add_argument("--maps", type=int, default=10000)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=16)
@@ -262,8 +288,8 @@ def main(argv=None):
     kw = dict(max_iters=a.max_iters, area_source=a.area_source)
     if a.cmd == "train":
         t1 = time.perf_counter()
-        X = torch.empty((a.maps, N_TEX, N_TEX, 3), dtype=torch.float32, device="cuda")
-        Y = torch.empty((a.maps, N_TEX, N_TEX, 2), dtype=torch.float32, device="cuda")
+        X = torch.empty((a.maps, N_NET, N_NET, 3), dtype=torch.float32, device="cuda")
+        Y = torch.empty((a.maps, N_NET, N_NET, 2), dtype=torch.float32, device="cuda")
         its, sts, xis = [], [], []
         chunk = 1024
         for c0 in range(0, a.maps, chunk):
@@ -271,7 +297,7 @@ def main(argv=None):
             maps = make_maps(range(TRAIN_SEED0 + c0, TRAIN_SEED0 + c1), workers=a.workers)
             gm = [ctx.map_from(m) for m, s in maps]
             X[c0:c1] = features(ctx, maps, gmaps=gm, **kw)
-            Yc, st = plain_runs(ctx, maps, gmaps=gm, **kw)
+            Yc, st = plain_runs(ctx, maps, N_TEX, N_NET, gmaps=gm, **kw)
             Y[c0:c1] = Yc
             its.append(st["iters"])
             sts.append(st["status"])
@@ -297,7 +323,7 @@ def main(argv=None):
             maps = make_maps(range(TEST_SEED0, TEST_SEED0 + a.eval_maps), workers=a.workers)
             report["eval"] = compare(ctx, net, maps, single=a.single, **kw)
     else:
-        net = B.Net(ctx, max_batch=8, **NET_CFG)
+        net = B.Net(ctx, max_batch=PREDICT_BATCH, **NET_CFG)
         net.load(a.weights)
         maps = make_maps(range(TEST_SEED0, TEST_SEED0 + a.maps), workers=a.workers)
         report = compare(ctx, net, maps, single=a.single, **kw)

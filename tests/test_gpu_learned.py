@@ -17,8 +17,10 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from paper_2604_13880_amd.learned import WEIGHTS_NAME
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-WEIGHTS = os.path.join(ROOT, "paper_2604_13880_amd", "weights", "warm_start_512.bin")
+WEIGHTS = os.path.join(ROOT, "paper_2604_13880_amd", "weights", WEIGHTS_NAME)
 
 
 def test_learned_warm_start_gain():
@@ -27,7 +29,7 @@ def test_learned_warm_start_gain():
     from paper_2604_13880_amd import learned as Lr
     assert os.path.exists(WEIGHTS), "trained weights are part of the repository"
     ctx = B.Context(0)
-    net = B.Net(ctx, max_batch=8, **Lr.NET_CFG)
+    net = B.Net(ctx, max_batch=Lr.PREDICT_BATCH, **Lr.NET_CFG)
     net.load(WEIGHTS)
     maps = Lr.make_maps(range(Lr.TEST_SEED0, Lr.TEST_SEED0 + 32), workers=8)
     rep = Lr.compare(ctx, net, maps, area_source=1)

@@ -31,6 +31,24 @@ def test_log_density_matches_oracle(ctx):
         assert np.max(np.abs(got - want)) < 1e-5
 
 
+def test_log_density_of_several_maps_in_one_call(ctx):
+    """The batched call gives, for every map, the texture of the single-map
+    calls (same kernels: bit-equal), and the oracle's within 1e-5."""
+    import torch
+    N = 128
+    maps = [(voronoi_map(1100 + k, 12 + 9 * k, 800 + 400 * k, fractal=k % 2 == 1),
+             lognormal_values(1100 + k, 12 + 9 * k, 1.0).astype(np.float32)) for k in range(3)]
+    gms = [ctx.map_from(m) for m, s in maps]
+    got = ctx.log_density_maps(gms, [torch.from_numpy(m.xy32()).cuda() for m, s in maps], N,
+                               [torch.from_numpy(s).cuda() for m, s in maps], shape=0.8).cpu().numpy()
+    for k, ((m, s), gm) in enumerate(zip(maps, gms)):
+        lab, cnt, _ = ctx.rasterize(gm, m.xy32(), N)
+        one = ctx.log_density(lab, cnt, torch.from_numpy(s).cuda(), shape=0.8).cpu().numpy()
+        assert np.array_equal(got[k], one)
+        want = oc.log_density(lab.cpu().numpy().view(np.uint16), cnt.cpu().numpy(), s.astype(np.float64), b=0.8)
+        assert np.max(np.abs(got[k] - want)) < 1e-5
+
+
 def test_tracer_grid_and_field(ctx):
     import torch
     G = 64
