@@ -63,27 +63,35 @@ def make_maps(seeds, rmin=50, rmax=150, per_region=250, sigma=1.0, workers=16):
         return pool.map(_make_map, args, chunksize=max(1, len(args) // (4 * workers)))
 
 
-def net_inputs(ctx, maps, N=N_NET, shape=1.0, gmaps=None, batch=64):
+def device_inputs(maps):
+    """Positions and values of every map on the device: two uploads, one
+    view per map (reused by every call on the same maps)."""
+    import torch
+    xy = torch.from_numpy(np.concatenate([m.xy32() for m, s in maps])).cuda()
+    vals = torch.from_numpy(np.concatenate([s for m, s in maps]).astype(np.float32)).cuda()
+    xys, vs, o, r = [], [], 0, 0
+    for m, s in maps:
+        xys.append(xy[o:o + m.n_vertices])
+        vs.append(vals[r:r + len(s)])
+        o += m.n_vertices
+        r += len(s)
+    return xys, vs
+
+
+def net_inputs(ctx, maps, N=N_NET, shape=1.0, gmaps=None, batch=64, dev=None):
     """log-density textures [n][N][N] (device float32) of the original maps,
     `batch` maps per library call (positions and values uploaded at once)."""
     import torch
     out = torch.empty((len(maps), N, N), dtype=torch.float32, device="cuda")
+    xys, vs = device_inputs(maps) if dev is None else dev
     for b0 in range(0, len(maps), batch):
         part = maps[b0:b0 + batch]
         gm = [ctx.map_from(m) for m, s in part] if gmaps is None else gmaps[b0:b0 + batch]
-        xy = torch.from_numpy(np.concatenate([m.xy32() for m, s in part])).cuda()
-        vals = torch.from_numpy(np.concatenate([s for m, s in part]).astype(np.float32)).cuda()
-        xys, vs, o, r = [], [], 0, 0
-        for m, s in part:
-            xys.append(xy[o:o + m.n_vertices])
-            vs.append(vals[r:r + len(s)])
-            o += m.n_vertices
-            r += len(s)
-        out[b0:b0 + len(part)] = ctx.log_density_maps(gm, xys, N, vs, shape=shape)
+        out[b0:b0 + len(part)] = ctx.log_density_maps(gm, xys[b0:b0 + batch], N, vs[b0:b0 + batch], shape=shape)
     return out
 
 
-def plain_runs(ctx, maps, N=N_TEX, G=N_TEX, batch=32, graph_iters=8, gmaps=None, **kw):
+def plain_runs(ctx, maps, N=N_TEX, G=N_TEX, batch=32, graph_iters=8, gmaps=None, dev=None, **kw):
     """Plain runs to the stopping rule with a G x G tracer grid; returns the
     tracer displacement fields [n][G][G][2] (device) and per-map stats."""
     import torch
@@ -94,7 +102,11 @@ def plain_runs(ctx, maps, N=N_TEX, G=N_TEX, batch=32, graph_iters=8, gmaps=None,
     for b0 in range(0, len(maps), batch):
         part = maps[b0:b0 + batch]
         gm = [ctx.map_from(m) for m, s in part] if gmaps is None else gmaps[b0:b0 + batch]
-        descs = [dict(map=g, xy0=m.xy32(), N=N, values=s, extra=grid, **kw) for g, (m, s) in zip(gm, part)]
+        if dev is None:
+            descs = [dict(map=g, xy0=m.xy32(), N=N, values=s, extra=grid, **kw) for g, (m, s) in zip(gm, part)]
+        else:
+            descs = [dict(map=g, xy0=dev[0][b0 + k], N=N, values=dev[1][b0 + k], extra=grid, **kw)
+                     for k, g in enumerate(gm)]
         res = ctx.step_series(descs, graph_iters=graph_iters)
         for k, r in enumerate(res):
             fields[b0 + k] = ctx.tracer_field(G, r["extra_xy"][0])
@@ -104,16 +116,18 @@ def plain_runs(ctx, maps, N=N_TEX, G=N_TEX, batch=32, graph_iters=8, gmaps=None,
     return fields, stats
 
 
-def features(ctx, maps, N=N_TEX, G=N_NET, gmaps=None, **kw):
+def features(ctx, maps, N=N_TEX, G=N_NET, gmaps=None, dev=None, **kw):
     """Net input [n][G][G][3]: log-density on the G x G grid and the
     displacement of a G x G tracer grid after FEATURE_ITERS plain
     iterations at texture N (same stopping parameters otherwise)."""
     import torch
     kw = dict(kw)
     kw.pop("max_iters", None)
-    X0 = net_inputs(ctx, maps, G, gmaps=gmaps)
+    dev = device_inputs(maps) if dev is None else dev
+    X0 = net_inputs(ctx, maps, G, gmaps=gmaps, dev=dev)
     # a few iterations: eager launches (a captured graph would cost more than it saves)
-    D, _ = plain_runs(ctx, maps, N, G, gmaps=gmaps, graph_iters=-FEATURE_ITERS, fixed_iters=FEATURE_ITERS, **kw)
+    D, _ = plain_runs(ctx, maps, N, G, gmaps=gmaps, dev=dev, graph_iters=-FEATURE_ITERS, fixed_iters=FEATURE_ITERS,
+                      **kw)
     return torch.cat([X0[..., None], D], dim=-1).contiguous()
 
 
@@ -164,14 +178,17 @@ def predict(net, X, batch=PREDICT_BATCH, pool=1):
     return out
 
 
-def run_batched(ctx, gmaps, maps, fields=None, N=N_TEX, batch=32, graph_iters=8, **kw):
+def run_batched(ctx, gmaps, maps, fields=None, N=N_TEX, batch=32, graph_iters=8, dev=None, **kw):
     """Runs of many maps, `batch` cartograms per cg_step_series call."""
     out = dict(iters=[], status=[], xi=[], flags=[])
     for b0 in range(0, len(maps), batch):
         descs = []
         for k in range(b0, min(b0 + batch, len(maps))):
             m, s = maps[k]
-            d = dict(map=gmaps[k], xy0=m.xy32(), N=N, values=s, **kw)
+            if dev is None:
+                d = dict(map=gmaps[k], xy0=m.xy32(), N=N, values=s, **kw)
+            else:
+                d = dict(map=gmaps[k], xy0=dev[0][k], N=N, values=dev[1][k], **kw)
             if fields is not None:
                 d["init_field"] = fields[k]
             descs.append(d)
@@ -192,21 +209,23 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
     import torch
     gmaps = [ctx.map_from(m) for m, s in maps]
     n = len(maps)
+    dev = device_inputs(maps)   # positions and values on the device, for both sides
+    dv = lambda a, b: (dev[0][a:b], dev[1][a:b])
     # untimed first calls of both paths (buffer allocation, code loading)
     k0 = min(n, 4)
-    run_batched(ctx, gmaps[:k0], maps[:k0], None, N, batch, graph_iters, **kw)
-    Fw = predict(net, features(ctx, maps[:k0], N, gmaps=gmaps[:k0], **kw), pool=WARM_POOL)
-    run_batched(ctx, gmaps[:k0], maps[:k0], Fw, N, batch, graph_iters, **kw)
+    run_batched(ctx, gmaps[:k0], maps[:k0], None, N, batch, graph_iters, dev=dv(0, k0), **kw)
+    Fw = predict(net, features(ctx, maps[:k0], N, gmaps=gmaps[:k0], dev=dv(0, k0), **kw), pool=WARM_POOL)
+    run_batched(ctx, gmaps[:k0], maps[:k0], Fw, N, batch, graph_iters, dev=dv(0, k0), **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = run_batched(ctx, gmaps, maps, None, N, batch, graph_iters, **kw)
+    plain = run_batched(ctx, gmaps, maps, None, N, batch, graph_iters, dev=dev, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    X = features(ctx, maps, N, gmaps=gmaps, **kw)
+    X = features(ctx, maps, N, gmaps=gmaps, dev=dev, **kw)
     F = predict(net, X, pool=WARM_POOL)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    warm = run_batched(ctx, gmaps, maps, F, N, batch, graph_iters, **kw)
+    warm = run_batched(ctx, gmaps, maps, F, N, batch, graph_iters, dev=dev, **kw)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     # equal quality: per-map tolerance = the plain run's final max error
@@ -221,8 +240,7 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
         for b0 in range(0, n, batch):
             descs = []
             for k in range(b0, min(b0 + batch, n)):
-                m, s = maps[k]
-                d = dict(map=gmaps[k], xy0=m.xy32(), N=N, values=s, tol=float(tol[k]), **kq)
+                d = dict(map=gmaps[k], xy0=dev[0][k], N=N, values=dev[1][k], tol=float(tol[k]), **kq)
                 if fields is not None:
                     d["init_field"] = fields[k]
                 descs.append(d)
@@ -257,7 +275,7 @@ def compare(ctx, net, maps, N=N_TEX, batch=32, graph_iters=8, single=0, **kw):
         k = min(single, n)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
-        run_batched(ctx, gmaps[:k], maps[:k], None, N, 1, graph_iters, **kw)
+        run_batched(ctx, gmaps[:k], maps[:k], None, N, 1, graph_iters, dev=dv(0, k), **kw)
         torch.cuda.synchronize()
         rep["plain_single_ms_per_cartogram"] = (time.perf_counter() - t4) * 1e3 / k
     return rep
