@@ -298,6 +298,7 @@ def main(argv=None):
     ap.add_argument("--area-source", type=int, default=1, help="0 pixel counts, 1 polygon areas")
     ap.add_argument("--eval-maps", type=int, default=0, help="after training, compare on this many held-out maps")
     ap.add_argument("--single", type=int, default=0, help="also time the plain method one cartogram per call")
+    ap.add_argument("--base-channels", type=int, default=NET_CFG["base_channels"])
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
@@ -326,7 +327,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"training data in {time.perf_counter() - t1:.1f}s: iterations mean {st['iters'].mean():.1f}, "
             f"converged {(st['status'] == 0).sum()}, xi mean {st['xi'].mean():.4f}")
-        net = B.Net(ctx, max_batch=max(a.batch, 8), seed=1, **NET_CFG)
+        cfg = dict(NET_CFG, base_channels=a.base_channels)
+        net = B.Net(ctx, max_batch=max(a.batch, 8), seed=1, **cfg)
         t2 = time.perf_counter()
         hist = train(net, X, Y, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log, max_seconds=a.max_train_seconds)
         torch.cuda.synchronize()
@@ -341,7 +343,7 @@ def main(argv=None):
             maps = make_maps(range(TEST_SEED0, TEST_SEED0 + a.eval_maps), workers=a.workers)
             report["eval"] = compare(ctx, net, maps, single=a.single, **kw)
     else:
-        net = B.Net(ctx, max_batch=PREDICT_BATCH, **NET_CFG)
+        net = B.Net(ctx, max_batch=PREDICT_BATCH, **dict(NET_CFG, base_channels=a.base_channels))
         net.load(a.weights)
         maps = make_maps(range(TEST_SEED0, TEST_SEED0 + a.maps), workers=a.workers)
         report = compare(ctx, net, maps, single=a.single, **kw)
