@@ -394,3 +394,39 @@ def test_uneven_batch_equals_single_runs_and_oracle(ctx):
         want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, s.astype(np.float64), N)
         err = np.abs(_np(one[k]["xy"])[0].astype(np.float64) - want).max()
         assert err <= 1e-6, (k, err)
+
+
+def _comb_map(teeth: int):
+    """One region whose upper side is a square wave of `teeth` teeth between
+    y = 0.4 and 0.6: every row in that band is crossed 2 * teeth times."""
+    from synth import PlanarMap
+    pts = [(0.1, 0.1), (0.9, 0.1), (0.9, 0.4)]
+    dx = 0.8 / teeth
+    for i in range(teeth):
+        x0 = 0.9 - i * dx
+        pts += [(x0, 0.6), (x0 - dx / 2, 0.6), (x0 - dx / 2, 0.4)]
+        if i + 1 < teeth:
+            pts.append((x0 - dx, 0.4))
+    pts.append((0.1, 0.4))
+    xy = np.asarray(pts, dtype=np.float32).astype(np.float64)
+    ring = np.arange(len(pts), dtype=np.int32)
+    a = 0.5 * np.sum(xy[ring, 0] * np.roll(xy[ring, 1], -1) - np.roll(xy[ring, 0], -1) * xy[ring, 1])
+    if a < 0:
+        ring = ring[::-1].copy()
+    return PlanarMap(xy=xy, ring_off=np.array([0, len(pts)], dtype=np.int32), ring_idx=ring,
+                     ring_reg=np.array([1], dtype=np.int32), n_regions=1)
+
+
+def test_row_bucket_overflow_is_reported(ctx):
+    """A row crossed more often than its bucket holds (256 crossings) makes
+    the series report CG_FLAG_OVERFLOW and end with CG_STATUS_ERROR; a map
+    just under the limit runs normally."""
+    from paper_2604_13880_amd import binding as B
+    for teeth, over in ((150, True), (100, False)):
+        m = _comb_map(teeth)
+        gm = ctx.map_from(m)
+        r = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=256, values=np.array([1.0], np.float32),
+                                  fixed_iters=2)])[0]
+        flagged = bool(r["flags"][0] & B.FLAG_OVERFLOW)
+        assert flagged == over, (teeth, r["flags"][0])
+        assert (r["status"][0] == B.STATUS_ERROR) == over
