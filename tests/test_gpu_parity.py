@@ -341,9 +341,11 @@ def test_shape_parameter(ctx):
         assert np.abs(nxt - want).max() <= 1e-6
 
 
-@pytest.mark.parametrize("shape", [(128, 32), (256, 32)])
+@pytest.mark.parametrize("shape", [(128, 32), (256, 32), (128, 16)])
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_integral_image_labels_2048(ctx, prec, shape):
+    # (128, 16) at 2048^2: the tile-row prefix table (128 x 17) exceeds the
+    # carry pass's LDS table, so the separate row-carry pass runs
     """Labels + LUT at 2048^2 (the size of the batched series) for every accumulation mode."""
     m = voronoi_map(3000, 200, 200000, fractal=True)
     N = 2048
@@ -430,3 +432,26 @@ def test_row_bucket_overflow_is_reported(ctx):
         flagged = bool(r["flags"][0] & B.FLAG_OVERFLOW)
         assert flagged == over, (teeth, r["flags"][0])
         assert (r["status"][0] == B.STATUS_ERROR) == over
+
+
+def test_large_batch_with_separate_density_pass(ctx):
+    """A batch whose LUT work (tiles x LUT entries) exceeds what the reduce
+    pass builds itself runs Step 3 as its own launch: one iteration still
+    matches the oracle, and a single (fused) run of the same map to rounding."""
+    import torch
+    m = voronoi_map(4200, 300, 30000, fractal=False)
+    N, n = 1024, 8
+    vals = [lognormal_values(4200 + k, 300, 1.0).astype(np.float32) for k in range(n)]
+    gm = ctx.map_from(m)
+    descs = [dict(map=gm, xy0=m.xy32(), N=N, values=v, fixed_iters=1) for v in vals]
+    ctx.set_tile_shape(N, 1, n * N * N, 128, 16)      # 8 x 512 tiles x 301 entries > 2^20
+    ctx.set_tile_shape(N, 1, N * N, 128, 16)
+    say("large batch, separate density pass")
+    batch = ctx.step_series(descs)
+    single = ctx.step_series([descs[0]])[0]
+    assert np.abs(_np(single["xy"]) - _np(batch[0]["xy"])).max() <= 1e-6
+    for k in (0, 5):
+        want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, vals[k].astype(np.float64), N)
+        err = np.abs(_np(batch[k]["xy"])[0].astype(np.float64) - want).max()
+        assert err <= 1e-6, (k, err)
+
