@@ -72,9 +72,10 @@ __global__ __launch_bounds__(256) void k_density(Batch B) {
   }
 }
 
-// Step 1 in closed form: t(x, y; d0) for a constant density, from the
-// quadrant areas (products) and wedge areas (squares minus the parts the
-// domain border cuts off), combined by eq.(2).
+// The anchor points of eq.(2) at (x, y).  Step 1's t(x, y; d0) for a
+// constant density is in closed form (quadrant areas are products, wedge
+// areas squares minus the parts the domain border cuts off) and enters
+// node_disp below.
 template <typename F>
 __device__ __forceinline__ void anchors(F x, F y, F& q1x, F& q1y, F& q2x, F& q2y, F& q3x, F& q3y,
                                         F& q4x, F& q4y) {
@@ -84,38 +85,33 @@ __device__ __forceinline__ void anchors(F x, F y, F& q1x, F& q1y, F& q2x, F& q2y
   else { q2x = 1; q2y = x + y - 1; q4x = x + y - 1; q4y = 1; }
 }
 
-template <typename F>
-__device__ __forceinline__ F sqp(F z) { return z > F(0) ? z * z : F(0); }
-
-template <typename F>
-__device__ __forceinline__ void t_uniform(F x, F y, F q1x, F q1y, F q2x, F q2y, F q3x, F q3y, F q4x,
-                                          F q4y, F& tx, F& ty) {
-  const F h = F(0.5);
-  const F a = x * y, b = x * (1 - y), g = (1 - x) * (1 - y), d = (1 - x) * y;
-  const F at = y * y - h * sqp(y - x) - h * sqp(x + y - 1);
-  const F bt = x * x - h * sqp(x - y) - h * sqp(x + y - 1);
-  const F gt = (1 - y) * (1 - y) - h * sqp(1 - x - y) - h * sqp(x - y);
-  const F dt = (1 - x) * (1 - x) - h * sqp(1 - x - y) - h * sqp(y - x);
-  tx = h * (a * q1x + b * q2x + g * q3x + d * q4x + (at + gt) * x + bt);
-  ty = h * (a * q1y + b * q2y + g * q3y + d * q4y + at + (bt + dt) * y);
-}
-
 // Step 5 at one node (x, y) = (i, j) / N: D = t(.; d) - t(.; d0)
 // (eqs.(2)-(3)) from the node's S and T, S at (i, N) and (N, j), the
 // diagonal marginals HA[i + j] and HB[j - i + N], the total C and 1/(2C).
 template <typename F>
 __device__ __forceinline__ void node_disp(F x, F y, F s, F tt, F siN, F sNj, F ha, F hb, F C, F inv2C, F& dx,
                                           F& dy) {
-  const F a = s, b = siN - s, dl = sNj - s, g = C - siN - sNj + s;
-  const F at = tt, bt = ha - tt, dt = hb - tt, gt = C - ha - hb + tt;
+  // eq.(2) for the density and for the constant density in one
+  // combination: each coefficient is (integral / 2C) - (its constant-
+  // density value / 2); the wedge areas need the squared positive parts
+  // of z and -z for both diagonals: one max and one min each (one of the
+  // two is zero)
+  const F h = F(0.5);
+  const F u = y - x, w = x + y - 1;
+  const F up = fmax(u, F(0)), un = fmin(u, F(0)), wp = fmax(w, F(0)), wn = fmin(w, F(0));
+  const F su = up * up, sv = un * un, sw = wp * wp, sz = wn * wn;   // wedges of y-x, x-y, x+y-1, 1-x-y
+  const F a = s * inv2C - h * (x * y);
+  const F b = (siN - s) * inv2C - h * (x * (1 - y));
+  const F dl = (sNj - s) * inv2C - h * ((1 - x) * y);
+  const F g = (C - siN - sNj + s) * inv2C - h * ((1 - x) * (1 - y));
+  const F at = tt * inv2C - h * (y * y - h * su - h * sw);
+  const F bt = (ha - tt) * inv2C - h * (x * x - h * sv - h * sw);
+  const F gt = (C - ha - hb + tt) * inv2C - h * ((1 - y) * (1 - y) - h * sz - h * sv);
+  const F dt = (hb - tt) * inv2C - h * ((1 - x) * (1 - x) - h * sz - h * su);
   F q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y;
   anchors(x, y, q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y);
-  const F tx = (a * q1x + b * q2x + g * q3x + dl * q4x + (at + gt) * x + bt) * inv2C;
-  const F ty = (a * q1y + b * q2y + g * q3y + dl * q4y + at + (bt + dt) * y) * inv2C;
-  F ux, uy;
-  t_uniform(x, y, q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y, ux, uy);
-  dx = tx - ux;
-  dy = ty - uy;
+  dx = a * q1x + b * q2x + g * q3x + dl * q4x + (at + gt) * x + bt;
+  dy = a * q1y + b * q2y + g * q3y + dl * q4y + at + (bt + dt) * y;
 }
 
 // (S, T) of node (i, j): one load of the interleaved pair (ST = 2) or two.
