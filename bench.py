@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--workload", default="fractal100_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=24)
-    ap.add_argument("--graph-iters", type=int, default=-8,
+    ap.add_argument("--graph-iters", type=int, default=-32,
                     help="iterations between convergence polls; negative = eager launches "
                          "(HIP events around the timed stage are only recorded outside graphs)")
     ap.add_argument("--stage", default="sat_final", choices=sorted(KERNEL_SOURCES),

@@ -118,7 +118,24 @@ struct Plan {
   int64_t edge_blocks = 0, row_blocks = 0, tiles = 0, c1 = 0, c2 = 0, pt_blocks = 0, reg_blocks = 0;
   IterState* d_state = nullptr;
   std::vector<Inst> inst;
+  bool fuse_lut = false;    // Step 3 built by the integral-image reduce pass (see lut_fusable)
 };
+
+// Step 3 inside the integral-image reduce pass (one launch fewer) when
+// every LUT fits its LDS and the redundant per-block builds are cheap:
+// tiles x LUT entries summed over the batch up to 2^20 (measured: a single
+// 1024^2 cartogram gains 5 us per iteration, a 64 x 2048^2 batch would
+// lose 24 us).
+bool lut_fusable(const Plan& P) {
+  bool fuse = !P.dense;
+  int64_t work = 0;
+  for (const Inst& I : P.inst) {
+    fuse = fuse && I.n_lut == I.R + 1 && I.n_lut <= cgk::kLutLds;
+    const cgk::SatLayout L = cgk::sat_layout(I.N, P.tw, P.th);
+    work += (int64_t)L.ntx * L.nty * I.n_lut;
+  }
+  return fuse && work <= ((int64_t)1 << 20);
+}
 
 int64_t pitch_of(int N) { return (int64_t)((N + 1 + 63) / 64) * 64; }
 
@@ -369,19 +386,7 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   void* u = prof ? (void*)&hc : nullptr;
   auto hk = [&](int s, int after) { if (h) h(s, after, u); };
   cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, h, u);
-  // Step 3 inside the integral-image reduce pass (one launch fewer) when
-  // every LUT fits its LDS and the redundant per-block builds are cheap:
-  // tiles x LUT entries summed over the batch up to 2^20 (measured: a
-  // single 1024^2 cartogram gains 5 us per iteration, a 64 x 2048^2 batch
-  // would lose 24 us)
-  bool fuse = !P.dense;
-  int64_t work = 0;
-  for (const Inst& I : P.inst) {
-    fuse = fuse && I.n_lut == I.R + 1 && I.n_lut <= cgk::kLutLds;
-    const cgk::SatLayout L = cgk::sat_layout(I.N, P.tw, P.th);
-    work += (int64_t)L.ntx * L.nty * I.n_lut;
-  }
-  fuse = fuse && work <= ((int64_t)1 << 20);
+  const bool fuse = P.fuse_lut;
   cgk::Batch Bl = P.B;
   if (fuse) {
     Bl.make_lut = 1;
@@ -440,6 +445,8 @@ int cg_destroy(cg_ctx* c) {
     if (kv.second.p) hipFree(kv.second.p);
   if (c->pinned) hipHostFree(c->pinned);
   if (c->pinned_ev) hipEventDestroy(c->pinned_ev);
+  for (auto& e : c->graphs) hipGraphExecDestroy(e.exec);
+  if (c->st_pinned) hipHostFree(c->st_pinned);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
   return CG_OK;
@@ -909,6 +916,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
   Plan P;
   int rc = build_plan(c, specs, prec, tw, th, false, nd, st, P, "series");
   if (rc) return rc;
+  P.fuse_lut = lut_fusable(P);
   const int n = P.n;
   cgk::launch_init(P.B, P.pt_blocks, st);
   bool warm = false;
@@ -951,15 +959,59 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     c->prof_rec.assign(K, 0);
     c->prof_stream = st;
   }
+  bool cached = false;   // exec belongs to the context's graph cache
   if (!eager) {
-    HIP_OK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-    for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
-    HIP_OK(c, hipStreamEndCapture(st, &graph));
-    HIP_OK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    // the captured iteration reads every per-call value (descriptors,
+    // states) from device memory: a call with the same launches (same
+    // batch descriptor, buffer addresses, grids, tile shape, chunk length,
+    // stream) replays the graph instantiated for an earlier one
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.B = P.B;
+    key.prec = P.prec;
+    key.tw = P.tw;
+    key.th = P.th;
+    key.il = P.il ? 1 : 0;
+    key.fuse = P.fuse_lut ? 1 : 0;
+    key.K = K;
+    key.blocks[0] = P.edge_blocks;
+    key.blocks[1] = P.row_blocks;
+    key.blocks[2] = P.tiles;
+    key.blocks[3] = P.c1;
+    key.blocks[4] = P.c2;
+    key.blocks[5] = P.pt_blocks;
+    key.blocks[6] = P.reg_blocks;
+    key.stream = st;
+    if (!prof)
+      for (auto& e : c->graphs)
+        if (memcmp(&e.key, &key, sizeof(key)) == 0) {
+          exec = e.exec;
+          cached = true;
+        }
+    if (!exec) {
+      HIP_OK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
+      HIP_OK(c, hipStreamEndCapture(st, &graph));
+      HIP_OK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      if (!prof) {
+        if (c->graphs.size() >= 8) {   // keep the most recent few
+          (void)hipGraphExecDestroy(c->graphs.front().exec);
+          c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back(GraphEntry{key, exec});
+        cached = true;
+      }
+    }
   }
   std::vector<IterState> hs(n);
-  IterState* pinned = nullptr;
-  HIP_OK(c, hipHostMalloc((void**)&pinned, sizeof(IterState) * n, hipHostMallocDefault));
+  if (c->st_pinned_n < (size_t)n) {   // pinned state buffer of the convergence polls, kept by the context
+    if (c->st_pinned) (void)hipHostFree(c->st_pinned);
+    c->st_pinned = nullptr;
+    c->st_pinned_n = 0;
+    HIP_OK(c, hipHostMalloc(&c->st_pinned, sizeof(IterState) * n, hipHostMallocDefault));
+    c->st_pinned_n = n;
+  }
+  IterState* pinned = (IterState*)c->st_pinned;
   int max_budget = 0;
   for (auto& s : specs) max_budget = std::max(max_budget, s.fixed_iters > 0 ? s.fixed_iters : s.max_iters);
   int launched = 0;
@@ -1002,8 +1054,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     launched += K;
   }
   memcpy(hs.data(), pinned, sizeof(IterState) * n);
-  hipHostFree(pinned);
-  if (exec) hipGraphExecDestroy(exec);
+  if (exec && !cached) hipGraphExecDestroy(exec);
   if (graph) hipGraphDestroy(graph);
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "cg.h"
+#include "cg_dev.h"
 
 namespace cgh {
 
@@ -34,6 +35,18 @@ struct cg_map {
   int32_t* d_reg_rings = nullptr;
 };
 
+// Launch parameters of a captured iteration graph (compared bytewise).
+struct GraphKey {
+  cgk::Batch B;
+  int32_t prec, tw, th, il, fuse, K;
+  int64_t blocks[7];
+  hipStream_t stream;
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
 struct cg_ctx {
   int device = 0;
   hipStream_t stream = nullptr;  // private stream of the series driver (graph capture)
@@ -56,6 +69,10 @@ struct cg_ctx {
   int64_t prof_launches = 0;
   int64_t prof_failed = 0;
   hipStream_t prof_stream = nullptr;
+  // series driver: instantiated iteration graphs, pinned state buffer
+  std::vector<GraphEntry> graphs;
+  void* st_pinned = nullptr;
+  size_t st_pinned_n = 0;
 };
 
 namespace cgh {
