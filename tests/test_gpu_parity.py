@@ -455,3 +455,26 @@ def test_large_batch_with_separate_density_pass(ctx):
         err = np.abs(_np(batch[k]["xy"])[0].astype(np.float64) - want).max()
         assert err <= 1e-6, (k, err)
 
+
+
+def test_cached_iteration_graph_reads_the_new_call(ctx):
+    """A second call with the same launches replays the first call's graph:
+    it must compute from its own inputs (bit-equal to a fresh context and to
+    eager launches)."""
+    from paper_2604_13880_amd import binding as B
+    m = voronoi_map(4300, 24, 3000, fractal=True)
+    s1 = lognormal_values(4300, 24, 1.0).astype(np.float32)
+    s2 = lognormal_values(4301, 24, 1.5).astype(np.float32)
+    gm = ctx.map_from(m)
+    d = lambda s: dict(map=gm, xy0=m.xy32(), N=256, values=s, fixed_iters=12)
+    r1 = ctx.step_series([d(s1)], graph_iters=4)[0]
+    r2 = ctx.step_series([d(s2)], graph_iters=4)[0]        # same launches: the cached graph
+    fresh = B.Context(0)
+    try:
+        f2 = fresh.step_series([dict(d(s2), map=fresh.map_from(m))], graph_iters=4)[0]
+    finally:
+        fresh.close()
+    e2 = ctx.step_series([d(s2)], graph_iters=-4)[0]
+    assert not np.array_equal(_np(r1["xy"]), _np(r2["xy"]))
+    assert np.array_equal(_np(r2["xy"]), _np(f2["xy"]))
+    assert np.array_equal(_np(r2["xy"]), _np(e2["xy"]))
