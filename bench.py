@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fractal100_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=24)
+    ap.add_argument("--cpu-iters", type=int, default=96)
     ap.add_argument("--graph-iters", type=int, default=-32,
                     help="iterations between convergence polls; negative = eager launches "
                          "(HIP events around the timed stage are only recorded outside graphs)")

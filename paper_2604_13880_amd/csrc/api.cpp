@@ -306,6 +306,12 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   B.max_n = 0;
   for (int k = 0; k < n; ++k) B.max_n = std::max(B.max_n, (int32_t)P.inst[k].N);
   B.make_lut = 0;
+  for (int kd = 0; kd < cgk::KD_COUNT; ++kd) {   // equal block counts: instance = block / count
+    const int64_t s = kind(kd)[1] - kind(kd)[0];
+    bool eq = s > 0 && s < INT32_MAX;
+    for (int k = 1; eq && k < n; ++k) eq = kind(kd)[k + 1] - kind(kd)[k] == s;
+    B.stride[kd] = eq ? (int32_t)s : 0;
+  }
   B.off_edges = doff + 0 * (n + 1);
   B.off_rows = doff + 1 * (n + 1);
   B.off_tiles = doff + 2 * (n + 1);

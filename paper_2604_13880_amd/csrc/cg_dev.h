@@ -103,12 +103,16 @@ using InstG = InstT<GlobalPtr>;
 static_assert(sizeof(Inst) == sizeof(InstG), "descriptor views share one layout");
 
 // Per-kind block offsets over the instances of a batch ([n+1] each).
+// Kinds of per-instance work; each has its own block numbering.
+enum Kind { KD_EDGES = 0, KD_ROWS, KD_TILES, KD_CARRY1, KD_CARRY2, KD_PTS, KD_REGIONS, KD_INST, KD_COUNT };
+
 struct Batch {
   const Inst* inst;
   int32_t n;
   int32_t skip_done;                  // 1: instances whose state says done are skipped
   int32_t max_n;                      // largest texture of the batch
   int32_t make_lut;                   // 1: the integral-image reduce pass builds the density LUT (Step 3)
+  int32_t stride[KD_COUNT];           // blocks per instance of each kind when all instances have as many, else 0
   const int64_t* off_edges;
   const int64_t* off_rows;
   const int64_t* off_tiles;
@@ -119,15 +123,26 @@ struct Batch {
   const int64_t* off_inst;
 };
 
-// Instance of a (block-uniform) work index; the result is made explicitly
-// wave-uniform so descriptor fields are fetched with scalar loads.
-__device__ __forceinline__ int find_inst(const int64_t* off, int n, int64_t b) {
-  int lo = 0, hi = n;
+// Instance of block b of work kind kd, and that instance's first block.
+// When every instance has the same number of blocks of the kind this is a
+// division; otherwise a binary search over the block offsets `off`.  The
+// instance is made explicitly wave-uniform so descriptor fields are fetched
+// with scalar loads.
+__device__ __forceinline__ int find_inst(const Batch& B, const int64_t* off, int kd, int64_t b, int64_t& first) {
+  const uint32_t s = (uint32_t)B.stride[kd];
+  if (s > 0u) {   // block indices are below 2^32
+    const int k = __builtin_amdgcn_readfirstlane((int)((uint32_t)b / s));
+    first = (int64_t)k * s;
+    return k;
+  }
+  int lo = 0, hi = B.n;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
     if (off[mid] <= b) lo = mid; else hi = mid;
   }
-  return __builtin_amdgcn_readfirstlane(lo);
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  first = off[lo];
+  return lo;
 }
 
 // Descriptor k of a batch in registers (scalar loads; read-only in kernels).

@@ -35,7 +35,8 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // background density b*d0; the LUT is scaled so the texture mass is N^2
 // (the map is invariant to a common scale of the density).
 __global__ __launch_bounds__(256) void k_density(Batch B) {
-  const int k = find_inst(B.off_inst, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_inst, KD_INST, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
@@ -133,10 +134,11 @@ __device__ __forceinline__ void node_st(g_ptr<const F> S, g_ptr<const F> T, int6
 // values, two values of row N and two of column N.
 template <typename F, int ST>
 __global__ __launch_bounds__(256) void k_map_points(Batch B) {
-  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_pts, KD_PTS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   g_ptr<float2> ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
   const float2 p = ld2(ptr);
@@ -186,10 +188,11 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
 // centres), then clamp to the unit square.  alpha < 0: the instance's
 // chosen step (IterState::ws_alpha; 0 = no move).
 __global__ __launch_bounds__(256) void k_apply_field(Batch B, float alpha) {
-  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_pts, KD_PTS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   const float a = alpha < 0.f ? I.st->ws_alpha : alpha;
   if (a == 0.f) return;
@@ -218,10 +221,11 @@ __global__ __launch_bounds__(256) void k_apply_field(Batch B, float alpha) {
 
 // Warm start: put the starting positions back (before the next trial step).
 __global__ __launch_bounds__(256) void k_restore(Batch B) {
-  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_pts, KD_PTS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (I.init_field == nullptr) return;
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   if (idx < I.n_vert) {
     if (I.src_xy && I.src_xy != I.xy) st2(I.xy + idx, ld2(I.src_xy + idx));
@@ -297,11 +301,12 @@ __global__ __launch_bounds__(256) void k_tracer_field(int G, const float2* fin, 
 
 // Shoelace area of every region (sum over its rings), FP64, fixed order.
 __global__ __launch_bounds__(256) void k_areas(Batch B) {
-  const int k = find_inst(B.off_regions, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_regions, KD_REGIONS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
-  const int v = 1 + (int)(blockIdx.x - B.off_regions[k]);
+  const int v = 1 + (int)(blockIdx.x - first);
   const int t = threadIdx.x;
   double acc = 0.0;
   for (int rr = I.reg_ring_off[v - 1]; rr < I.reg_ring_off[v]; ++rr) {
@@ -324,7 +329,8 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
 // start, 3 records a trial step `alpha` if it is the best so far, 4 flags
 // CG_FLAG_FALLBACK when no trial step beat the plain start.
 __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
-  const int k = find_inst(B.off_inst, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_inst, KD_INST, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ double red[256];
@@ -397,9 +403,10 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
 
 // Reset the iteration state and copy the starting positions.
 __global__ __launch_bounds__(256) void k_init(Batch B) {
-  const int k = find_inst(B.off_pts, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_pts, KD_PTS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_pts[k]) * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (idx == 0) {
     IterState z = {};
     z.best_xi = 1e300;
@@ -411,7 +418,7 @@ __global__ __launch_bounds__(256) void k_init(Batch B) {
   // the row counters are accumulated with atomics and cleared by their
   // consumers; scratch memory starts with arbitrary contents
   if (I.row_cnt) {
-    const int64_t nth = (B.off_pts[k + 1] - B.off_pts[k]) * 256;
+    const int64_t nth = (B.off_pts[k + 1] - first) * 256;
     for (int64_t q = idx; q < I.N; q += nth) I.row_cnt[q] = 0u;
   }
   if (idx >= I.n_pts) return;

@@ -33,14 +33,15 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
 }
 
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
-  const int k = find_inst(B.off_edges, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_edges, KD_EDGES, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
-  if (blockIdx.x == B.off_edges[k]) {   // the instance's first block: clear the fill's totals
+  if (blockIdx.x == first) {   // the instance's first block: clear the fill's totals
     for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
     if (threadIdx.x == 0) I.st->contested = 0;
   }
-  const int64_t e = (int64_t)(blockIdx.x - B.off_edges[k]) * 256 + threadIdx.x;
+  const int64_t e = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (e >= I.n_edges) return;
   const int4 E = ld4(I.edges + e);
   const int N = I.N;
@@ -167,7 +168,8 @@ __device__ __forceinline__ uint32_t bitonic_sort(uint32_t key, int lane) {
 // fail this test, or have several crossings at one p0, take the exact
 // serial walk instead (folded maps, coincident crossings).
 __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
-  const int k = find_inst(B.off_rows, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_rows, KD_ROWS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   constexpr int RPW = kFillRows / 4;   // rows per wavefront
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   __shared__ unsigned long long contested_blk;
   const int N = I.N, R = I.R;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int q0 = (int)(blockIdx.x - B.off_rows[k]) * kFillRows;
+  const int q0 = (int)(blockIdx.x - first) * kFillRows;
   const bool lds_counts = (R + 1) <= kLutLds;
   if (lds_counts)
     for (int v = t; v <= R; v += 256) lcount[v] = 0u;
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
         pk.y = v[2] | ((uint32_t)v[3] << 16);
         pk.z = v[4] | ((uint32_t)v[5] << 16);
         pk.w = v[6] | ((uint32_t)v[7] << 16);
-        *(g_ptr<u32x4_t>)(row + p) = pk;     // N is a multiple of 8
+        __builtin_nontemporal_store(pk, (g_ptr<u32x4_t>)(row + p));   // N is a multiple of 8; streamed
         }
       }
       if (lane == 0) I.row_cnt[q] = 0u;

@@ -247,12 +247,16 @@ __device__ __forceinline__ Lc seg_inclusive_scan_dpp(Lc x) {
 
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-// Buffer store of a 4, 8 or 16-byte value at voff + soff bytes.
+// Buffer store of a 4, 8 or 16-byte value at voff + soff bytes, marked
+// nontemporal (cache policy bit 1): the tables are written once and read
+// by the next kernel, so they should not displace the labels and LUT
+// that the writer's blocks are still reading.
 template <typename T>
 __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
-  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs, voff, soff, 0);
-  else if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, voff, soff, 0);
-  else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, soff, 0);
+  constexpr int kNT = 2;
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs, voff, soff, kNT);
+  else if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, voff, soff, kNT);
+  else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, soff, kNT);
 }
 // Eight consecutive LDS values (16-byte aligned) in 16-byte stores.
 __device__ __forceinline__ void store8(float* p, const float v[8]) {
@@ -404,9 +408,9 @@ template <int P, int TW, int TH, bool DENSE>
 __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
-  const int64_t nb = B.off_tiles[B.n];
-  const int64_t b = xcd_block(blockIdx.x, nb);
-  const int k = find_inst(B.off_tiles, B.n, b);
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);   // one block per tile of the batch
+  int64_t first;
+  const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   constexpr int NW = TW / 64, D = TW + TH - 1, SB = (kReduce_Rows < TH ? kReduce_Rows : TH), E = TW / 64;
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   __shared__ float lut_s[kLutLds];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const SatLayout L = sat_layout(I.N, TW, TH);
-  const int tile = (int)(b - B.off_tiles[k]);
+  const int tile = (int)(b - first);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
@@ -508,11 +512,12 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
 template <int P, int TW, int TH>
 __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
   typedef typename PT<P>::carry Cy;
-  const int k = find_inst(B.off_carry1, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_carry1, KD_CARRY1, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   const SatLayout L = sat_layout(I.N, TW, TH);
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_carry1[k]) * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   if (idx < L.NY) {
     const int q = (int)idx;
@@ -574,7 +579,8 @@ template <int P, int TW, int TH, bool PREF_LDS>
 __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
-  const int k = find_inst(B.off_carry2, B.n, blockIdx.x);
+  int64_t first;
+  const int k = find_inst(B, B.off_carry2, KD_CARRY2, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ Cy part[256];
@@ -599,7 +605,7 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   const int N = I.N, nty = L.nty;
   const int CH = L.carry_ch, IPB = 256 / CH;
   const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
-  const int64_t idx = (int64_t)(blockIdx.x - B.off_carry2[k]) * IPB + j;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * IPB + j;
   g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
   g_ptr<Cy> carry = (g_ptr<Cy>)I.carry;
   const int64_t nS = L.NX + 1;
@@ -689,9 +695,9 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   constexpr int NW = TW / 64, SB = kSub_Rows;
   constexpr int XW = TW + 2 * TH;          // columns x0-TH .. x0+TW+TH-1
   constexpr int NSL = TW + TH + 1;         // anti-diagonal / diagonal slots
-  const int64_t nb = B.off_tiles[B.n];
-  const int64_t b = xcd_block(blockIdx.x, nb);
-  const int k = find_inst(B.off_tiles, B.n, b);
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);   // one block per tile of the batch
+  int64_t first;
+  const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, I)) return;
   __shared__ __align__(16) Lc Pn[SB][TW];      // exclusive row prefix (from strip column TH) at node columns
@@ -704,7 +710,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int N = I.N;
   const SatLayout L = sat_layout(N, TW, TH);
-  const int tile = (int)(b - B.off_tiles[k]);
+  const int tile = (int)(b - first);
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
