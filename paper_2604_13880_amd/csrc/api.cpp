@@ -285,20 +285,47 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
         1};
     for (int kd = 0; kd < 8; ++kd) kind(kd)[k + 1] = kind(kd)[k] + cnt[kd];
   }
+  // per kind: a block's instance is block / stride when every instance has
+  // `stride` blocks of the kind; otherwise a table holds (instance, its
+  // first block) for every block of the kind
+  int32_t stride[cgk::KD_COUNT];
+  size_t tab_at[cgk::KD_COUNT];
+  size_t tab_words = 0;
+  for (int kd = 0; kd < cgk::KD_COUNT; ++kd) {
+    if (kind(kd)[n] > (int64_t)UINT32_MAX) return fail(c, CG_EINVAL, "batch too large: more than 2^32 blocks of one kind");
+    const int64_t s0 = kind(kd)[1] - kind(kd)[0];
+    bool eq = s0 > 0 && s0 < INT32_MAX;
+    for (int k = 1; eq && k < n; ++k) eq = kind(kd)[k + 1] - kind(kd)[k] == s0;
+    stride[kd] = eq ? (int32_t)s0 : 0;
+    tab_at[kd] = tab_words;
+    if (!eq) tab_words += 2 * (size_t)kind(kd)[n];
+  }
   const size_t inst_bytes = align_up(sizeof(Inst) * n);
   const size_t off_bytes = align_up(sizeof(int64_t) * offs.size());
+  const size_t tab_bytes = align_up(sizeof(uint32_t) * tab_words);
   const size_t st_bytes = align_up(sizeof(IterState) * n);
   char* desc = nullptr;
-  rc = get_buf(c, (std::string(tag) + ":desc").c_str(), inst_bytes + off_bytes + st_bytes, st, &desc);
+  rc = get_buf(c, (std::string(tag) + ":desc").c_str(), inst_bytes + off_bytes + tab_bytes + st_bytes, st, &desc);
   if (rc) return rc;
-  P.d_state = (IterState*)(desc + inst_bytes + off_bytes);
+  P.d_state = (IterState*)(desc + inst_bytes + off_bytes + tab_bytes);
   for (int k = 0; k < n; ++k) P.inst[k].st = P.d_state + k;
-  std::vector<char> host(inst_bytes + off_bytes, 0);
+  std::vector<char> host(inst_bytes + off_bytes + tab_bytes, 0);
   memcpy(host.data(), P.inst.data(), sizeof(Inst) * n);
   memcpy(host.data() + inst_bytes, offs.data(), sizeof(int64_t) * offs.size());
+  uint32_t* tab = (uint32_t*)(host.data() + inst_bytes + off_bytes);
+  for (int kd = 0; kd < cgk::KD_COUNT; ++kd) {
+    if (stride[kd]) continue;
+    uint32_t* t = tab + tab_at[kd];
+    for (int k = 0; k < n; ++k)
+      for (int64_t b = kind(kd)[k]; b < kind(kd)[k + 1]; ++b) {
+        t[2 * b] = (uint32_t)k;
+        t[2 * b + 1] = (uint32_t)kind(kd)[k];
+      }
+  }
   rc = upload(c, desc, host.data(), host.size(), st);
   if (rc) return rc;
   const int64_t* doff = (const int64_t*)(desc + inst_bytes);
+  const uint32_t* dtab = (const uint32_t*)(desc + inst_bytes + off_bytes);
   Batch& B = P.B;
   B.inst = (const Inst*)desc;
   B.n = n;
@@ -306,11 +333,10 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   B.max_n = 0;
   for (int k = 0; k < n; ++k) B.max_n = std::max(B.max_n, (int32_t)P.inst[k].N);
   B.make_lut = 0;
-  for (int kd = 0; kd < cgk::KD_COUNT; ++kd) {   // equal block counts: instance = block / count
-    const int64_t s = kind(kd)[1] - kind(kd)[0];
-    bool eq = s > 0 && s < INT32_MAX;
-    for (int k = 1; eq && k < n; ++k) eq = kind(kd)[k + 1] - kind(kd)[k] == s;
-    B.stride[kd] = eq ? (int32_t)s : 0;
+  B.states = P.d_state;
+  for (int kd = 0; kd < cgk::KD_COUNT; ++kd) {
+    B.stride[kd] = stride[kd];
+    B.where[kd] = stride[kd] ? nullptr : dtab + tab_at[kd];
   }
   B.off_edges = doff + 0 * (n + 1);
   B.off_rows = doff + 1 * (n + 1);

@@ -113,6 +113,8 @@ struct Batch {
   int32_t max_n;                      // largest texture of the batch
   int32_t make_lut;                   // 1: the integral-image reduce pass builds the density LUT (Step 3)
   int32_t stride[KD_COUNT];           // blocks per instance of each kind when all instances have as many, else 0
+  const IterState* states;            // [n] iteration states (instance k's is states + k)
+  const uint32_t* where[KD_COUNT];    // stride 0: per block of the kind, (instance, its first block)
   const int64_t* off_edges;
   const int64_t* off_rows;
   const int64_t* off_tiles;
@@ -125,15 +127,22 @@ struct Batch {
 
 // Instance of block b of work kind kd, and that instance's first block.
 // When every instance has the same number of blocks of the kind this is a
-// division; otherwise a binary search over the block offsets `off`.  The
-// instance is made explicitly wave-uniform so descriptor fields are fetched
-// with scalar loads.
+// division; otherwise one load from the batch's block table (a binary
+// search over the block offsets `off` if there is none).  The instance is
+// made explicitly wave-uniform so descriptor fields are fetched with
+// scalar loads.
 __device__ __forceinline__ int find_inst(const Batch& B, const int64_t* off, int kd, int64_t b, int64_t& first) {
   const uint32_t s = (uint32_t)B.stride[kd];
   if (s > 0u) {   // block indices are below 2^32
     const int k = __builtin_amdgcn_readfirstlane((int)((uint32_t)b / s));
     first = (int64_t)k * s;
     return k;
+  }
+  if (B.where[kd] != nullptr) {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    const u2 e = ((const u2 CG_CONST*)B.where[kd])[b];
+    first = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)e.y);
+    return __builtin_amdgcn_readfirstlane((int)e.x);
   }
   int lo = 0, hi = B.n;
   while (hi - lo > 1) {
@@ -176,8 +185,11 @@ __device__ __forceinline__ T g_atomic_or(g_ptr<T> p, T v) {
   return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool inst_done(const Batch& B, const InstG& I) {
-  return B.skip_done && I.st != nullptr && I.st->done != 0;
+// Whether instance k has met its stopping rule (skipped when the batch
+// says so).  Read from the state array directly, so the load does not wait
+// for the descriptor's.
+__device__ __forceinline__ bool inst_done(const Batch& B, int k) {
+  return B.skip_done && ((g_ptr<const IterState>)B.states)[k].done != 0;
 }
 
 __device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {  // b > 0

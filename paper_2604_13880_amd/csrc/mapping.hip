@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_density(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_inst, KD_INST, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
   auto count = [&](int v) -> double { return (double)I.counts[v]; };
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_map_points(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_pts, KD_PTS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   if (idx >= I.n_pts) return;
   g_ptr<float2> ptr = idx < I.n_vert ? I.xy + idx : I.extra + (idx - I.n_vert);
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_regions, KD_REGIONS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   __shared__ double red[256];
   const int v = 1 + (int)(blockIdx.x - first);
   const int t = threadIdx.x;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   int64_t first;
   const int k = find_inst(B, B.off_inst, KD_INST, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
   double sa = 0.0, ss = 0.0;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_edges, KD_EDGES, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   if (blockIdx.x == first) {   // the instance's first block: clear the fill's totals
     for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
     if (threadIdx.x == 0) I.st->contested = 0;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_rows, KD_ROWS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   constexpr int RPW = kFillRows / 4;   // rows per wavefront
   __shared__ uint64_t xs[4][kFillXing];
   __shared__ uint64_t srt[4][kFillXing];

@@ -412,7 +412,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   constexpr int NW = TW / 64, D = TW + TH - 1, SB = (kReduce_Rows < TH ? kReduce_Rows : TH), E = TW / 64;
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
   static_assert(TH % SB == 0, "whole sub-bands");
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_carry1, KD_CARRY1, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int64_t idx = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
   g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_carry2, KD_CARRY2, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   __shared__ Cy part[256];
   __shared__ Cy partC[256];
   __shared__ Cy pref_s[PREF_LDS ? kPrefLds : 1];
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
-  if (inst_done(B, I)) return;
+  if (inst_done(B, k)) return;
   __shared__ __align__(16) Lc Pn[SB][TW];      // exclusive row prefix (from strip column TH) at node columns
   __shared__ __align__(16) Lc Ml[SB][XW];      // Mloc of the sub-band's rows
   __shared__ Lc la_s[SB][NSL];
