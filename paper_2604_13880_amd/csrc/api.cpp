@@ -25,7 +25,7 @@
 #include "host.h"
 
 namespace cgk {
-void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
+void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u);
 bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, bool il, int64_t tiles, int64_t c1,
                 int64_t c2, hipStream_t s, StageHook h, void* u);
@@ -119,6 +119,7 @@ struct Plan {
   IterState* d_state = nullptr;
   std::vector<Inst> inst;
   bool fuse_lut = false;    // Step 3 built by the integral-image reduce pass (see lut_fusable)
+  int emit_ept = 1;         // edges per thread of the rasteriser's emit pass
 };
 
 // Step 3 inside the integral-image reduce pass (one launch fewer) when
@@ -269,13 +270,23 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   // descriptors, offsets and states in one device buffer
   std::vector<int64_t> offs(8 * (size_t)(n + 1), 0);
   auto kind = [&](int kd) { return offs.data() + (size_t)kd * (n + 1); };
+  // edges per emit thread: several once a launch holds many rounds of
+  // blocks (more than 8192 single-edge blocks, 2M edges; measured: emit of
+  // 64 x 2048^2 125 -> 90 us with 4, while a 1024^2 cartogram's 196 blocks
+  // take 8 -> 12 us)
+  {
+    int64_t blocks1 = 0;
+    for (const Inst& I : P.inst) blocks1 += std::max<int64_t>(1, (I.n_edges + 255) / 256);
+    P.emit_ept = blocks1 > 8192 ? cgk::kEmitEdges : 1;
+  }
+  const int64_t edges_per_block = 256 * (int64_t)P.emit_ept;
   for (int k = 0; k < n; ++k) {
     const Inst& I = P.inst[k];
     SatLayout L = cgk::sat_layout(I.N, tw, th);
     // every instance gets an edge block: its first one clears the totals
     // the rasteriser's fill accumulates
     const int64_t cnt[8] = {
-        std::max<int64_t>(1, (I.n_edges + 255) / 256),
+        std::max<int64_t>(1, (I.n_edges + edges_per_block - 1) / edges_per_block),
         (I.N + kFillRows - 1) / kFillRows,
         (int64_t)L.ntx * L.nty,
         (L.NY + L.nty + 1 + 255) / 256,
@@ -417,7 +428,7 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   cgk::StageHook h = prof ? prof_hook : nullptr;
   void* u = prof ? (void*)&hc : nullptr;
   auto hk = [&](int s, int after) { if (h) h(s, after, u); };
-  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, h, u);
+  cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, h, u);
   const bool fuse = P.fuse_lut;
   cgk::Batch Bl = P.B;
   if (fuse) {
@@ -590,7 +601,7 @@ int cg_rasterize(cg_ctx* c, const cg_map* map, const float* xy, int N, uint16_t*
   if (rc) return rc;
   P.B.skip_done = 0;
   cgk::launch_init(P.B, P.pt_blocks, st);
-  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+  cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
   if (contested) cgk::launch_export(P.B, contested, nullptr, st);
   return check_launch(c);
 }
@@ -880,7 +891,7 @@ int cg_log_density_maps(cg_ctx* c, int32_t n, const cg_map* const* maps, const f
   if (rc) return rc;
   P.B.skip_done = 0;
   cgk::launch_init(P.B, P.pt_blocks, st);
-  cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+  cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
   char* lut = nullptr;
   if ((rc = get_buf(c, "log_lut", sizeof(float) * (size_t)(maxR + 1), st, &lut))) return rc;
   for (int k = 0; k < n; ++k)   // stream order: each launch has the LUT scratch to itself
@@ -963,7 +974,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     for (float a : kAlphas) {
       cgk::launch_restore(P.B, P.pt_blocks, st);
       cgk::launch_apply_field(P.B, P.pt_blocks, a, st);
-      cgk::launch_raster(P.B, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
+      cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, nullptr, nullptr);
       cgk::launch_areas(P.B, P.reg_blocks, st);
       cgk::launch_err(P.B, 3, st, a);
     }
@@ -1006,6 +1017,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     key.il = P.il ? 1 : 0;
     key.fuse = P.fuse_lut ? 1 : 0;
     key.K = K;
+    key.ept = P.emit_ept;
     key.blocks[0] = P.edge_blocks;
     key.blocks[1] = P.row_blocks;
     key.blocks[2] = P.tiles;

@@ -17,6 +17,7 @@ constexpr int kSub = 256;          // fixed-point subdivisions per pixel (raster
 constexpr int kLutLds = 1024;      // LUT entries kept in LDS by the scan / fill kernels
 constexpr int kFillXing = 256;     // crossings one row may hold (its bucket; LDS of the fill kernel)
 constexpr int kSetCap = 8;         // simultaneous claims tracked per pixel run
+constexpr int kEmitEdges = 4;      // edges per emit thread in large launches
 constexpr int kFillRows = 4;       // label rows per fill block (one per wavefront)
 constexpr int kCarryRows = 8;      // tile rows one carry thread sums
 

@@ -38,7 +38,7 @@ struct cg_map {
 // Launch parameters of a captured iteration graph (compared bytewise).
 struct GraphKey {
   cgk::Batch B;
-  int32_t prec, tw, th, il, fuse, K;
+  int32_t prec, tw, th, il, fuse, K, ept, pad;
   int64_t blocks[7];
   hipStream_t stream;
 };

@@ -32,6 +32,10 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
   q1 = min((hi - kSub / 2 + kSub - 1) >> 8, N);
 }
 
+// One thread per EPT edges (e0 + 256 j): all their loads are issued before
+// any is used, which shortens the chain of dependent loads per edge when a
+// launch has many rounds of blocks.
+template <int EPT>
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_edges, KD_EDGES, blockIdx.x, first);
@@ -41,32 +45,43 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
     for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
     if (threadIdx.x == 0) I.st->contested = 0;
   }
-  const int64_t e = (int64_t)(blockIdx.x - first) * 256 + threadIdx.x;
-  if (e >= I.n_edges) return;
-  const int4 E = ld4(I.edges + e);
+  const int64_t e0 = (int64_t)(blockIdx.x - first) * (256 * EPT) + threadIdx.x;
+  if (e0 >= I.n_edges) return;
   const int N = I.N;
   const float scale = (float)(kSub * N);
-  const float2 pa = ld2(I.xy + E.x), pb = ld2(I.xy + E.y);
-  int ax = snapc(pa.x, scale), ay = snapc(pa.y, scale);
-  int bx = snapc(pb.x, scale), by = snapc(pb.y, scale);
-  int q0, q1;
-  crossed_rows(ay, by, N, q0, q1);
-  if (q0 >= q1) return;
-  if (ay > by) {  // orient so that dy > 0; the crossing abscissa is unchanged
-    int tx = ax; ax = bx; bx = tx;
-    int ty = ay; ay = by; by = ty;
+  int4 E[EPT];
+  float2 pa[EPT], pb[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) E[j] = ld4(I.edges + min(e0 + 256 * j, (int64_t)I.n_edges - 1));
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    pa[j] = ld2(I.xy + E[j].x);
+    pb[j] = ld2(I.xy + E[j].y);
   }
-  const int64_t dy = by - ay, dx = bx - ax;
-  const int64_t den = (int64_t)kSub * dy;
-  const uint64_t regs = ((uint64_t)(uint16_t)E.z << 16) | ((uint64_t)(uint16_t)E.w << 32);
-  for (int q = q0; q < q1; ++q) {
-    const int64_t yc = (int64_t)kSub * q + kSub / 2;
-    // centre p is at or right of the crossing iff 256 p dy >= num
-    const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
-    int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
-    if (p0 > N) p0 = N;
-    const uint32_t slot = g_atomic_add(&I.row_cnt[q], 1u);   // a full bucket is the fill's overflow
-    if (slot < (uint32_t)kFillXing) I.xing[(int64_t)q * kFillXing + slot] = (uint64_t)p0 | regs;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    if (e0 + 256 * j >= I.n_edges) break;
+    int ax = snapc(pa[j].x, scale), ay = snapc(pa[j].y, scale);
+    int bx = snapc(pb[j].x, scale), by = snapc(pb[j].y, scale);
+    int q0, q1;
+    crossed_rows(ay, by, N, q0, q1);
+    if (q0 >= q1) continue;
+    if (ay > by) {  // orient so that dy > 0; the crossing abscissa is unchanged
+      int tx = ax; ax = bx; bx = tx;
+      int ty = ay; ay = by; by = ty;
+    }
+    const int64_t dy = by - ay, dx = bx - ax;
+    const int64_t den = (int64_t)kSub * dy;
+    const uint64_t regs = ((uint64_t)(uint16_t)E[j].z << 16) | ((uint64_t)(uint16_t)E[j].w << 32);
+    for (int q = q0; q < q1; ++q) {
+      const int64_t yc = (int64_t)kSub * q + kSub / 2;
+      // centre p is at or right of the crossing iff 256 p dy >= num
+      const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
+      int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
+      if (p0 > N) p0 = N;
+      const uint32_t slot = g_atomic_add(&I.row_cnt[q], 1u);   // a full bucket is the fill's overflow
+      if (slot < (uint32_t)kFillXing) I.xing[(int64_t)q * kFillXing + slot] = (uint64_t)p0 | regs;
+    }
   }
 }
 
@@ -443,12 +458,13 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   if (t == 0 && contested_blk) g_atomic_add((g_ptr<unsigned long long>)&I.st->contested, (unsigned long long)contested_blk);
 }
 
-void launch_raster(const Batch& B, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
+void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u) {
   auto hk = [&](int st, int after) { if (h) h(st, after, u); };
   if (edge_blocks > 0) {
     hk(ST_RASTER_EMIT, 0);
-    hipLaunchKernelGGL(k_raster_emit, dim3(edge_blocks), dim3(256), 0, s, B);
+    if (ept == kEmitEdges) hipLaunchKernelGGL(k_raster_emit<kEmitEdges>, dim3(edge_blocks), dim3(256), 0, s, B);
+    else hipLaunchKernelGGL(k_raster_emit<1>, dim3(edge_blocks), dim3(256), 0, s, B);
     hk(ST_RASTER_EMIT, 1);
   }
   hk(ST_RASTER_FILL, 0);

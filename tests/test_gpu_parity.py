@@ -457,6 +457,29 @@ def test_large_batch_with_separate_density_pass(ctx):
 
 
 
+def test_large_batch_emits_several_edges_per_thread(ctx):
+    """A batch of more than 8192 blocks of 256 edges (2M edges) runs the
+    rasteriser's emit pass with several edges per thread: one iteration of
+    its first and last instances matches the oracle and a single run of the
+    same map (one edge per thread) to rounding."""
+    m = voronoi_map(2000, 100, 50000, fractal=True)
+    N, n = 1024, 48
+    vals = [lognormal_values(4400 + k, 100, 1.5).astype(np.float32) for k in range(n)]
+    gm = ctx.map_from(m)
+    assert n * ((gm.n_edges + 255) // 256) > 8192 and (gm.n_edges + 255) // 256 <= 8192
+    descs = [dict(map=gm, xy0=m.xy32(), N=N, values=v, fixed_iters=1) for v in vals]
+    ctx.set_tile_shape(N, 1, n * N * N, 128, 16)
+    ctx.set_tile_shape(N, 1, N * N, 128, 16)
+    say("large batch, several edges per emit thread")
+    batch = ctx.step_series(descs)
+    for k in (0, n - 1):
+        single = ctx.step_series([descs[k]])[0]
+        assert np.abs(_np(single["xy"]) - _np(batch[k]["xy"])).max() <= 1e-6
+        want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, vals[k].astype(np.float64), N)
+        err = np.abs(_np(batch[k]["xy"])[0].astype(np.float64) - want).max()
+        assert err <= 1e-6, (k, err)
+
+
 def test_cached_iteration_graph_reads_the_new_call(ctx):
     """A second call with the same launches replays the first call's graph:
     it must compute from its own inputs (bit-equal to a fresh context and to
