@@ -207,10 +207,8 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     I.density = s.density;
     if (s.map) {
       I.edges = s.map->d_edges;
-      I.ring_off = s.map->d_ring_off;
-      I.ring_idx = s.map->d_ring_idx;
-      I.reg_ring_off = s.map->d_reg_ring_off;
-      I.reg_rings = s.map->d_reg_rings;
+      I.reg_pair_off = s.map->d_reg_pair_off;
+      I.reg_pairs = s.map->d_reg_pairs;
     }
     // scratch offsets relative to the instance base (-1: caller buffer or unused)
     Own& ow = owns[k];
@@ -533,13 +531,19 @@ int cg_map_build(cg_ctx* c, int32_t n_vertices, int32_t n_regions, int32_t n_rin
     if (ra == rb) continue;  // both sides the same region: never changes membership
     edges.push_back(make_int4(kv.first.first, kv.first.second, ra, rb));
   }
-  // region -> rings CSR
-  std::vector<int32_t> reg_off(n_regions + 1, 0), reg_rings(n_rings);
-  for (int r = 0; r < n_rings; ++r) reg_off[ring_reg[r]]++;
+  // region -> ring edges (a, b), the rings of a region in input order: the
+  // shoelace sum of a region is one pass over a contiguous list
+  std::vector<int32_t> reg_off(n_regions + 1, 0);
+  for (int r = 0; r < n_rings; ++r) reg_off[ring_reg[r]] += ring_off[r + 1] - ring_off[r];
   for (int v = 1; v <= n_regions; ++v) reg_off[v] += reg_off[v - 1];
+  std::vector<int2> reg_pairs((size_t)total);
   {
     std::vector<int32_t> pos(reg_off.begin(), reg_off.end() - 1);
-    for (int r = 0; r < n_rings; ++r) reg_rings[pos[ring_reg[r] - 1]++] = r;
+    for (int r = 0; r < n_rings; ++r) {
+      const int beg = ring_off[r], len = ring_off[r + 1] - beg;
+      int32_t& p = pos[ring_reg[r] - 1];
+      for (int e = 0; e < len; ++e) reg_pairs[p++] = make_int2(ring_idx[beg + e], ring_idx[beg + (e + 1 == len ? 0 : e + 1)]);
+    }
   }
   cg_map* m = new cg_map();
   m->ctx = c;
@@ -554,10 +558,8 @@ int cg_map_build(cg_ctx* c, int32_t n_vertices, int32_t n_regions, int32_t n_rin
     return true;
   };
   bool ok = put((void**)&m->d_edges, edges.data(), sizeof(int4) * edges.size()) &&
-            put((void**)&m->d_ring_off, ring_off, sizeof(int32_t) * (n_rings + 1)) &&
-            put((void**)&m->d_ring_idx, ring_idx, sizeof(int32_t) * total) &&
-            put((void**)&m->d_reg_ring_off, reg_off.data(), sizeof(int32_t) * reg_off.size()) &&
-            put((void**)&m->d_reg_rings, reg_rings.data(), sizeof(int32_t) * reg_rings.size());
+            put((void**)&m->d_reg_pair_off, reg_off.data(), sizeof(int32_t) * reg_off.size()) &&
+            put((void**)&m->d_reg_pairs, reg_pairs.data(), sizeof(int2) * reg_pairs.size());
   if (!ok) {
     cg_map_destroy(m);
     return fail(c, CG_ENOMEM, "cg_map_build: device allocation failed");
@@ -571,10 +573,8 @@ int cg_map_destroy(cg_map* m) {
   if (m->ctx) hipSetDevice(m->ctx->device);
   hipDeviceSynchronize();
   hipFree(m->d_edges);
-  hipFree(m->d_ring_off);
-  hipFree(m->d_ring_idx);
-  hipFree(m->d_reg_ring_off);
-  hipFree(m->d_reg_rings);
+  hipFree(m->d_reg_pair_off);
+  hipFree(m->d_reg_pairs);
   delete m;
   return CG_OK;
 }

@@ -71,10 +71,8 @@ struct InstT {
   int64_t pitch;
   // topology
   typename PP::template p<const int4> edges;                  // (v0, v1, region A, region B)
-  typename PP::template p<const int32_t> ring_off;
-  typename PP::template p<const int32_t> ring_idx;
-  typename PP::template p<const int32_t> reg_ring_off;        // [R+1] region -> rings
-  typename PP::template p<const int32_t> reg_rings;
+  typename PP::template p<const int32_t> reg_pair_off;        // [R+1] region -> its ring edges
+  typename PP::template p<const int2> reg_pairs;              // ring edges (a, b) of every region, ring order
   // state and buffers
   typename PP::template p<float2> xy;                         // [n_vert] vertex positions (iterated in place)
   typename PP::template p<float2> extra;                      // [n_pts - n_vert] tracer points moved along

@@ -29,10 +29,8 @@ struct cg_map {
   cg_ctx* ctx = nullptr;
   int32_t n_vert = 0, R = 0, n_rings = 0, n_edges = 0;
   int4* d_edges = nullptr;
-  int32_t* d_ring_off = nullptr;
-  int32_t* d_ring_idx = nullptr;
-  int32_t* d_reg_ring_off = nullptr;
-  int32_t* d_reg_rings = nullptr;
+  int32_t* d_reg_pair_off = nullptr;   // [R+1] region -> its ring edges
+  int2* d_reg_pairs = nullptr;         // ring edges (a, b) grouped by region
 };
 
 // Launch parameters of a captured iteration graph (compared bytewise).

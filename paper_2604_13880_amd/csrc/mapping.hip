@@ -309,14 +309,12 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
   const int v = 1 + (int)(blockIdx.x - first);
   const int t = threadIdx.x;
   double acc = 0.0;
-  for (int rr = I.reg_ring_off[v - 1]; rr < I.reg_ring_off[v]; ++rr) {
-    const int r = I.reg_rings[rr];
-    const int beg = I.ring_off[r], len = I.ring_off[r + 1] - beg;
-    for (int e = t; e < len; e += 256) {
-      const float2 a = ld2(I.xy + I.ring_idx[beg + e]);
-      const float2 b = ld2(I.xy + I.ring_idx[beg + (e + 1 == len ? 0 : e + 1)]);
-      acc += (double)a.x * (double)b.y - (double)b.x * (double)a.y;
-    }
+  const int end = I.reg_pair_off[v];
+  for (int e = I.reg_pair_off[v - 1] + t; e < end; e += 256) {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    const i2 pr = *(g_ptr<const i2>)(I.reg_pairs + e);
+    const float2 a = ld2(I.xy + pr.x), b = ld2(I.xy + pr.y);
+    acc += (double)a.x * (double)b.y - (double)b.x * (double)a.y;
   }
   acc = block_sum(acc, red);
   if (t == 0) I.areas[v] = 0.5 * acc;
