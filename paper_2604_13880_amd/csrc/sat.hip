@@ -741,15 +741,18 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef typename Pair<St>::type St2;
   g_ptr<St> S = (g_ptr<St>)I.S;
   g_ptr<St> T = (g_ptr<St>)I.T;
-  g_ptr<St2> ST = (g_ptr<St2>)I.S;
   const int64_t pitch = I.pitch;
   const int i = x0 + t;
   // tiles are never wider than max(64, N) and the pitch holds every tile
   // column: columns past N are row padding, written without a bound check
   if (ty == 0) {
     if (IL) {
-      ST[i] = St2{(St)0, (St)0};
-      if (extra) ST[N] = St2{(St)0, (St)0};
+      S[2 * i] = (St)0;
+      S[2 * i + 1] = (St)0;
+      if (extra) {
+        S[2 * N] = (St)0;
+        S[2 * N + 1] = (St)0;
+      }
     } else {
       S[i] = (St)0;
       T[i] = (St)0;
@@ -769,6 +772,14 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   const int64_t tab_bytes = (int64_t)(N + 1) * I.pitch * (IL ? (int64_t)sizeof(St2) : (int64_t)sizeof(St));
   const __amdgpu_buffer_rsrc_t s_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.S, (short)0, (int)tab_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t t_rs = __builtin_amdgcn_make_buffer_rsrc(IL ? (void*)I.S : (void*)I.T, (short)0, (int)tab_bytes, 0x00020000);
+  // Interleaved (S, T) pairs of floats go out as one 8-byte store in the T
+  // pass.  Pairs of doubles are written in two phases, S in the sweep and T
+  // in the T pass (barriers between them, so the compiler cannot merge the
+  // halves): after a merged 16-byte store the compiler may rewrite the
+  // store's data registers in the next instruction, and with several writer
+  // blocks per CU such stores wrote the new values (double-precision series
+  // runs were not reproducible).
+  constexpr bool kSplit = IL && sizeof(St) == 8;
   // T of the rows of sub-band r0, from the slot sums of its sweep
   auto t_pass = [&](int r0) {
     // rows without branches between them, so their LDS reads can be batched
@@ -778,7 +789,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       const int sa = t + r + 1, sb = t + TH - 1 - r;
       A v = acc_sub(ca_s[sa], cb_s[sb]);
       acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-      if (IL) bstore(St2{sv[rr], (St)to_store(v)}, t_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
+      if (kSplit) bstore((St)to_store(v), t_rs, i * (int)sizeof(St2) + (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St2)));
+      else if (IL) bstore(St2{sv[rr], (St)to_store(v)}, t_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
       else bstore((St)to_store(v), t_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
     }
     if (xcol) {
@@ -790,7 +802,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
           const int sa = TW + r + 1, sb = TW + TH - 1 - r;
           A v = acc_sub(ca_s[sa], cb_s[sb]);
           acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-          if (IL) ST[row + N] = St2{svN[rr], (St)to_store(v)};
+          if (kSplit) S[2 * (row + N) + 1] = (St)to_store(v);
+          else if (IL) ((g_ptr<St2>)I.S)[row + N] = St2{svN[rr], (St)to_store(v)};
           else T[row + N] = to_store(v);
         }
       }
@@ -840,6 +853,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       acc_add_local(v, rsum);
       sv[rr] = (St)to_store(v);
       if (!IL) bstore(sv[rr], s_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
+      else if (kSplit) bstore(sv[rr], s_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
       la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
       lb0 += Ml[rr][t + r];                // diagonal slot t
       la_s[rr][t] = la0;
@@ -868,6 +882,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
           acc_add_local(v, rsumN);
           svN[rr] = (St)to_store(v);
           if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
+          else if (kSplit) S[2 * ((int64_t)j * pitch + N)] = svN[rr];
         }
       }
     }

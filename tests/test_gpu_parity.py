@@ -480,6 +480,25 @@ def test_large_batch_emits_several_edges_per_thread(ctx):
         assert err <= 1e-6, (k, err)
 
 
+def test_double_tables_with_several_writer_blocks_per_cu(ctx):
+    """Double-precision (S, T) pairs written by 512 writer blocks (several per
+    CU): repeated runs are bit-identical and agree with the float-stored
+    double-accumulated mode to float rounding."""
+    from paper_2604_13880_amd import binding as B
+    m = voronoi_map(2000, 100, 50000, fractal=True)
+    s = lognormal_values(2000, 100, 1.5).astype(np.float32)
+    gm = ctx.map_from(m)
+    N = 1024
+    for prec in (B.F64, B.F64ACC):
+        ctx.set_tile_shape(N, prec, N * N, 128, 16)
+    d = lambda prec: dict(map=gm, xy0=m.xy32(), N=N, values=s, precision=prec, fixed_iters=2)
+    say("double tables, 128x16 tiles at 1024^2")
+    runs = [_np(ctx.step_series([d(B.F64)], graph_iters=-1)[0]["xy"]) for _ in range(3)]
+    ref = _np(ctx.step_series([d(B.F64ACC)], graph_iters=-1)[0]["xy"])
+    assert all(np.array_equal(runs[0], r) for r in runs[1:])
+    assert np.abs(runs[0] - ref).max() <= 1e-6
+
+
 def test_cached_iteration_graph_reads_the_new_call(ctx):
     """A second call with the same launches replays the first call's graph:
     it must compute from its own inputs (bit-equal to a fresh context and to
