@@ -189,8 +189,8 @@ def run_learned(a, B, ctx, torch):
     rep = Lr.compare(ctx, net, maps, single=min(16, a.learned_maps), area_source=1)
     rep["workload"] = ("held-out seeded maps, 50-150 fractal Voronoi regions (~250 vertices per region), "
                        "lognormal sigma 1, 512^2 texture, polygon-area density, to max area error < 1% or the "
-                       "stopping rule; warm side = log-density on a 256^2 grid + one plain iteration (256^2 tracer "
-                       f"grid) + U-Net forward at 256^2 + graded warm start (field box-averaged to {Lr.N_NET // Lr.WARM_POOL}^2) + plain "
+                       f"stopping rule; warm side = log-density on a {Lr.N_NET}^2 grid + one plain iteration ({Lr.N_NET}^2 tracer "
+                       f"grid) + U-Net forward at {Lr.N_NET}^2 + graded warm start (field box-averaged to {Lr.N_NET // Lr.WARM_POOL}^2) + plain "
                        "iterations; 32 cartograms per call on both sides; equal quality: each map stopped at the "
                        "plain run's final max area error")
     rep["speedup_learned_batched_vs_plain_single"] = rep["plain_single_ms_per_cartogram"] / rep["warm_ms_per_cartogram"]

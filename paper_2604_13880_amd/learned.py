@@ -34,11 +34,11 @@ if ROOT not in sys.path:
 TRAIN_SEED0 = 5_000_000     # training maps: seeds TRAIN_SEED0 + k
 TEST_SEED0 = 6_000_000      # held-out maps
 N_TEX = 512              # texture of the cartograms
-N_NET = 256              # grid of the net's input and output (pixel centres of a 256^2 grid)
+N_NET = 128              # grid of the net's input and output (pixel centres of a 128^2 grid)
 FEATURE_ITERS = 1
-WARM_POOL = 4            # the predicted field is box-averaged over 4 x 4 cells (a 64^2 field) before use
+WARM_POOL = 2            # the predicted field is box-averaged over 2 x 2 cells (a 64^2 field) before use
 PREDICT_BATCH = 32
-WEIGHTS_NAME = "warm_start_256.bin"
+WEIGHTS_NAME = "warm_start_128.bin"
 RESIDUAL_GAIN = 2.4      # median ratio of the final to the first-iteration displacement on training maps
 NET_CFG = dict(base_channels=32, levels=4, height=N_NET, width=N_NET, out_scale=0.1, in_channels=3,
                residual_gain=RESIDUAL_GAIN)
