@@ -480,6 +480,30 @@ def test_large_batch_emits_several_edges_per_thread(ctx):
         assert err <= 1e-6, (k, err)
 
 
+def test_series_at_full_size_matches_oracle(ctx):
+    """The 64-step 2048^2 series as the benchmark runs it (one instance per
+    step in one batch, FP64-accumulated integral images, 256x64 tiles, four
+    edges per emit thread): one iteration of sampled steps matches the
+    oracle."""
+    from paper_2604_13880_amd import binding as B
+    from synth import random_walk_series
+    m = voronoi_map(3000, 200, 200000, fractal=True)
+    S = random_walk_series(3000, 200, 64).astype(np.float32)
+    N, T = 2048, 64
+    gm = ctx.map_from(m)
+    assert T * ((gm.n_edges + 255) // 256) > 8192
+    ctx.set_tile_shape(N, B.F64ACC, T * N * N, 256, 64)
+    say("series 64 x 2048^2, one iteration")
+    r = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=S, precision=B.F64ACC, fixed_iters=1)])[0]
+    xy = _np(r["xy"])
+    assert xy.shape[0] == T
+    for t in (0, 31, 63):
+        want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, S[t].astype(np.float64), N)
+        err = np.abs(xy[t].astype(np.float64) - want).max()
+        say("  step", t, "max |dxy|", err)
+        assert err <= 1e-6, (t, err)
+
+
 def test_double_tables_with_several_writer_blocks_per_cu(ctx):
     """Double-precision (S, T) pairs written by 512 writer blocks (several per
     CU): repeated runs are bit-identical and agree with the float-stored
