@@ -504,6 +504,39 @@ def test_series_at_full_size_matches_oracle(ctx):
         assert err <= 1e-6, (t, err)
 
 
+def _uneven_instance(spec):
+    m = voronoi_map(spec["seed"], spec["R"], spec["n_target"], fractal=True)
+    return m, lognormal_values(spec["seed"], spec["R"], spec["sigma"]).astype(np.float32)
+
+
+def test_uneven_batch_at_full_size_matches_oracle(ctx):
+    """The 256-cartogram uneven batch as the benchmark runs it (textures
+    256^2 to 2048^2 in one launch per kernel, compensated FP32, 256x64
+    tiles, block tables for the unequal instances, four edges per emit
+    thread, the density table as its own launch): one iteration of sampled
+    instances of every texture size matches the oracle."""
+    import multiprocessing as mp
+    from synth import uneven_batch_specs
+    specs = uneven_batch_specs(4000, 256)
+    with mp.get_context("fork").Pool(16) as pool:
+        maps = pool.map(_uneven_instance, specs, chunksize=4)
+    Ns = [sp["N"] for sp in specs]
+    px = sum(N * N for N in Ns)
+    ctx.set_tile_shape(max(Ns), 1, px, 256, 64)
+    descs = [dict(map=ctx.map_from(m), xy0=m.xy32(), N=N, values=v, precision=1, fixed_iters=1)
+             for (m, v), N in zip(maps, Ns)]
+    assert sum(d["map"].n_edges for d in descs) > 8192 * 256
+    say("uneven batch of", len(descs), "at full size, one iteration")
+    res = ctx.step_series(descs)
+    picks = [next(k for k, N in enumerate(Ns) if N == n) for n in sorted(set(Ns))]
+    for k in picks:
+        m, v = maps[k]
+        want, _ = oc.iterate_once(m.xy32().astype(np.float64), m, v.astype(np.float64), Ns[k])
+        err = np.abs(_np(res[k]["xy"])[0].astype(np.float64) - want).max()
+        say("  instance", k, "N", Ns[k], "max |dxy|", err)
+        assert err <= 1e-6, (k, Ns[k], err)
+
+
 def test_double_tables_with_several_writer_blocks_per_cu(ctx):
     """Double-precision (S, T) pairs written by 512 writer blocks (several per
     CU): repeated runs are bit-identical and agree with the float-stored
