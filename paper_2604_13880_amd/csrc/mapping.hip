@@ -5,28 +5,24 @@
 
 namespace cgk {
 
-// Fixed-order block reductions over 256 threads (deterministic).
+// Fixed-order block reductions over 256 threads (deterministic): a
+// butterfly of lane exchanges within each wavefront (lane 0's total is the
+// one used), then the four wavefront totals in a fixed order.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
 }
 __device__ __forceinline__ double block_max(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmax(red[t], red[t + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   __syncthreads();
   return r;
 }
