@@ -320,8 +320,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_per_copy": x.numel() * 4, "copies": 5}))
         return
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported in this build "
-              f"(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported: the library runs "
+              f"on one GPU (instances would shard across GPUs data-parallel)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -15,7 +15,7 @@ remark under eq.(1)):
   * integral images are the exact integrals of the piecewise-constant
     density over the summation areas with the node as corner or apex.
 
-Readings where the paper is silent (each is also listed in the design doc):
+Readings where the paper is silent:
   R1 integral images are node-based exact integrals (see above);
   R2 tilted areas: alpha_t = top wedge, beta_t = left, gamma_t = bottom,
      delta_t = right (pairing of the Fig. 2 caption with eq.(2));

@@ -1,6 +1,6 @@
 """GPU parity: every C-ABI call against the FP64 oracle on the same seeded
-inputs (labels and counts bit-exact; floating point within the bounds
-derived in the design doc)."""
+inputs (labels and counts bit-exact; floating point within bounds derived
+from the storage and accumulation precision of each mode)."""
 import os
 import sys
 
