@@ -74,7 +74,7 @@ def run_uneven(a, B, ctx, torch):
     descs = [dict(map=g, xy0=torch.from_numpy(m.xy32()).cuda(), N=sp["N"], values=torch.from_numpy(s).cuda(),
                   precision=w["precision"]) for g, (m, s), sp in zip(gms, maps, specs)]
     px = sum(sp["N"] ** 2 for sp in specs)
-    shape = ctx.autotune(2048, w["precision"], max(1, px // (2048 * 2048)))
+    shape = ctx.autotune(2048, w["precision"], max(1, px // (2048 * 2048)), cache_path=a.tune_cache)
     ctx.step_series(descs, graph_iters=a.graph_iters)      # warm-up
     torch.cuda.synchronize()
     ctx.profile_stage(a.stage, a.profile_every)
@@ -267,7 +267,7 @@ def run_series(a, w, B, ctx, torch):
     S = random_walk_series(w["seed"], w["R"], w["T"], sigma0=w["sigma"]).astype(np.float32)
     N = w["N"]
     gm = ctx.map_from(m)
-    shape = ctx.autotune(N, w["precision"], w["T"])
+    shape = ctx.autotune(N, w["precision"], w["T"], cache_path=a.tune_cache)
     desc = dict(map=gm, xy0=torch.from_numpy(m.xy32()).cuda(), N=N, values=torch.from_numpy(S).cuda(),
                 precision=w["precision"], frames=10)
     ctx.step_series([desc], graph_iters=a.graph_iters)
@@ -297,6 +297,8 @@ def main():
     ap.add_argument("--workload", default="fractal100_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=96)
+    ap.add_argument("--tune-cache", default=None,
+                    help="tile-shape table file: read if present, written otherwise (profiling runs share one)")
     ap.add_argument("--graph-iters", type=int, default=-32,
                     help="iterations between convergence polls; negative = eager launches "
                          "(HIP events around the timed stage are only recorded outside graphs)")
@@ -340,7 +342,7 @@ def main():
     descs = [dict(map=ctx.map_from(mk), xy0=torch.from_numpy(mk.xy32()).cuda(), N=N,
                   values=torch.from_numpy(vk).cuda(), precision=w["precision"], fixed_iters=w.get("fixed", 0))
              for mk, vk in maps]
-    tile = ctx.autotune(N, w["precision"], 1)
+    tile = ctx.autotune(N, w["precision"], 1, cache_path=a.tune_cache)
     torch.cuda.synchronize()
 
     warmup = max(a.warmup, nseed)          # every map once before the timed steps
