@@ -68,6 +68,8 @@ extern "C" {
 #define CG_FLAG_CONTESTED 1 /* a pixel centre was claimed by two regions: the map folded */
 #define CG_FLAG_OVERFLOW 2  /* a crossing buffer overflowed: results invalid */
 #define CG_FLAG_FALLBACK 4  /* a warm start was rejected and the plain start used */
+#define CG_FLAG_BADVALUES 8 /* a value is negative, infinite or NaN, or all are 0: the step is not
+                               iterated and ends with CG_STATUS_ERROR */
 
 typedef struct cg_ctx cg_ctx;
 typedef struct cg_map cg_map;

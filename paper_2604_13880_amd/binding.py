@@ -23,7 +23,7 @@ F32, COMP, F64, F64ACC = 0, 1, 2, 3
 DIRECT, CUMULATIVE = 0, 1
 AREA_PIXEL, AREA_POLYGON = 0, 1
 STATUS_CONVERGED, STATUS_STALLED, STATUS_MAXITER, STATUS_ERROR = 0, 1, 2, 3
-FLAG_CONTESTED, FLAG_OVERFLOW, FLAG_FALLBACK = 1, 2, 4
+FLAG_CONTESTED, FLAG_OVERFLOW, FLAG_FALLBACK, FLAG_BADVALUES = 1, 2, 4, 8
 
 
 class CgInim(C.Structure):

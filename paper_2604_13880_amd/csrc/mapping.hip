@@ -329,13 +329,16 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   if (inst_done(B, k)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
-  double sa = 0.0, ss = 0.0;
+  double sa = 0.0, ss = 0.0, bad = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
+    const float s = I.values[v - 1];
     sa += I.areas[v];
-    ss += (double)I.values[v - 1];
+    ss += (double)s;
+    bad = (s >= 0.f && s <= 3.4028235e38f) ? bad : 1.0;   // NaN, infinite or negative value
   }
   sa = block_sum(sa, red);
   ss = block_sum(ss, red);
+  bad = block_max(bad, red);
   double se = 0.0, me = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
     const double A = I.areas[v];
@@ -386,7 +389,11 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
     }
   }
   int done = 0, status = CG_STATUS_MAXITER;
-  if (st->flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
+  if (bad > 0.0 || !(ss > 0.0)) {   // the values define no density: nothing is iterated
+    st->flags |= CG_FLAG_BADVALUES;
+    done = 1;
+    status = CG_STATUS_ERROR;
+  } else if (st->flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
   else if (I.fixed_iters > 0) { done = it >= I.fixed_iters; status = CG_STATUS_MAXITER; }
   else if (xi < (double)I.tol) { done = 1; status = CG_STATUS_CONVERGED; }
   else if (it - st->best_k >= I.patience) { done = 1; status = CG_STATUS_STALLED; }

@@ -434,6 +434,73 @@ def test_row_bucket_overflow_is_reported(ctx):
         assert (r["status"][0] == B.STATUS_ERROR) == over
 
 
+def _folded_comb_map(teeth: int):
+    """The comb of `_comb_map` plus a second region, the rectangle
+    [0.3, 0.7] x [0.45, 0.55], laid over the teeth without sharing an edge:
+    the pixel centres inside both are claimed by two regions (a folded
+    map; they take the highest id), in rows crossed 2 * teeth + 2 times."""
+    from synth import PlanarMap
+    c = _comb_map(teeth)
+    n = c.xy.shape[0]
+    rect = np.array([[0.3, 0.45], [0.7, 0.45], [0.7, 0.55], [0.3, 0.55]], dtype=np.float32).astype(np.float64)
+    ring2 = np.arange(n, n + 4, dtype=np.int32)
+    return PlanarMap(xy=np.concatenate([c.xy, rect]), ring_off=np.array([0, n, n + 4], dtype=np.int32),
+                     ring_idx=np.concatenate([c.ring_idx, ring2]), ring_reg=np.array([1, 2], dtype=np.int32),
+                     n_regions=2)
+
+
+@pytest.mark.parametrize("case", ["comb40", "comb100", "folded_comb40", "folded_comb100"])
+def test_rows_beyond_64_crossings_bit_exact(ctx, case):
+    """Rows crossed more than 64 times take the fill kernel's serial walk of
+    the claim set: labels, counts and the contested count match the oracle
+    bit for bit (80 and 200 crossings per row; the folded combs add rows
+    where two regions claim the same runs)."""
+    teeth = int(case.rsplit("comb", 1)[1])
+    m = _folded_comb_map(teeth) if case.startswith("folded") else _comb_map(teeth)
+    gm = ctx.map_from(m)
+    for N in (256, 512):
+        say("long rows", case, "N", N)
+        lab, cnt, cont = ctx.rasterize(gm, m.xy32(), N)
+        want, wcnt, wconf = oc.rasterize(m.xy32().astype(np.float64), m.ring_off, m.ring_idx, m.ring_reg,
+                                         m.n_regions, N)
+        rows = [q for q in range(N) if 0.4 * N < q + 0.5 < 0.6 * N]
+        assert len(rows) > 0
+        np.testing.assert_array_equal(_labels_np(lab), want)
+        np.testing.assert_array_equal(_np(cnt), wcnt)
+        assert int(_np(cont)[0]) == wconf
+        assert (wconf > 0) == case.startswith("folded")
+
+
+def test_whole_run_1024_replays_match_oracle(ctx):
+    """Map 2000 of the 1024^2 workload (100 fractal regions, ~50k
+    vertices, compensated FP32) iterated on the GPU to 64, 256 and 511
+    iterations, the regime the benchmark runs (strongly deformed maps,
+    more crossings per row); from the GPU's own state at each point one
+    more iteration is replayed through the oracle: labels, counts and the
+    contested count bit-exact, moved positions within 1e-6."""
+    m = voronoi_map(2000, 100, 50000, fractal=True)
+    s = lognormal_values(2000, 100, 1.5).astype(np.float32)
+    N = 1024
+    gm = ctx.map_from(m)
+    xy = m.xy32()
+    done = 0
+    for k in (64, 256, 511):
+        r = ctx.step_series([dict(map=gm, xy0=xy, N=N, values=s, precision=1, fixed_iters=k - done)])[0]
+        assert int(r["iters"][0]) == k - done and int(r["flags"][0]) & 2 == 0
+        xy = _np(r["xy"])[0]
+        done = k
+        lab, cnt, cont = ctx.rasterize(gm, xy, N)
+        nxt, _ = _run1(ctx, gm, xy, N, s, prec=1)
+        want, info = oc.iterate_once(xy.astype(np.float64), m, s.astype(np.float64), N)
+        same = int((_labels_np(lab) == info["labels"]).sum())
+        err = np.abs(nxt.astype(np.float64) - want).max()
+        say(f"  after {k} iterations: labels equal {same}/{N * N}, contested {int(_np(cont)[0])}, max |dxy| {err:.2e}")
+        np.testing.assert_array_equal(_labels_np(lab), info["labels"])
+        np.testing.assert_array_equal(_np(cnt), info["counts"])
+        assert int(_np(cont)[0]) == info["conflicts"]
+        assert err <= 1e-6, (k, err)
+
+
 def test_large_batch_with_separate_density_pass(ctx):
     """A batch whose LUT work (tiles x LUT entries) exceeds what the reduce
     pass builds itself runs Step 3 as its own launch: one iteration still
