@@ -145,6 +145,23 @@ int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size
 int cg_integral_image(cg_ctx* ctx, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
                       const float* density, int precision, cg_inim* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * same operation as cg_integral_image, same arguments and results (bit
+ * for bit), but every temporary (tile aggregates, carries, the launch
+ * descriptors) lives in a static device buffer of 24 MiB that the library
+ * holds on each GPU until the process ends; the call itself allocates
+ * nothing and writes its descriptors with a kernel, not a host copy.  The
+ * buffer holds any N <= 2048 (at most 19 MB of scratch with the smallest
+ * tiles) and larger N with large enough tiles; a call whose scratch does
+ * not fit returns CG_EINVAL with the sizes in cg_last_error().  Every
+ * call on one GPU shares that buffer: calls that overlap on one GPU (on
+ * different streams, or from different contexts or threads without
+ * ordering) race and give undefined results.  CG_EDEVICE if the buffer's
+ * address could not be obtained when the context was created. */
+int cg_integral_image_noalloc(cg_ctx* ctx, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
+                              const float* density, int precision, cg_inim* out, void* stream);
+
 /* Steps 5-6: move n_points points by the DET displacement
  * D = t(.; d) - t(.; d0) of eqs.(2)-(3), evaluated at the four corner
  * nodes of each point from `inim` and interpolated bilinearly, then

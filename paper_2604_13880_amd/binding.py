@@ -74,6 +74,7 @@ def lib():
             "cg_rasterize": (C.c_int, [vp, vp, vp, C.c_int, vp, vp, vp, vp]),
             "cg_inim_size": (C.c_int, [C.c_int, C.c_int, C.POINTER(i64), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
             "cg_integral_image": (C.c_int, [vp, C.c_int, vp, vp, i32, vp, C.c_int, C.POINTER(CgInim), vp]),
+            "cg_integral_image_noalloc": (C.c_int, [vp, C.c_int, vp, vp, i32, vp, C.c_int, C.POINTER(CgInim), vp]),
             "cg_map_points": (C.c_int, [vp, C.POINTER(CgInim), vp, vp, i64, vp]),
             "cg_region_areas": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "cg_step_series": (C.c_int, [vp, C.POINTER(CgSeriesDesc), C.c_int, C.POINTER(CgSeriesOut), i32, vp]),
@@ -109,7 +110,8 @@ def lib():
 
 def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
-            "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_map_points",
+            "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_integral_image_noalloc",
+            "cg_map_points",
             "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
             "cg_profile_read", "cg_log_density", "cg_log_density_maps", "cg_tracer_field", "cg_field_pool", "cg_net_create", "cg_net_destroy",
             "cg_net_n_params", "cg_net_get_params", "cg_net_set_params", "cg_net_get_grads", "cg_net_zero_grads",
@@ -243,21 +245,25 @@ class Context:
         return Inim(int(N), int(precision), int(pitch.value), S, T, HA, HB)
 
     def integral_image(self, N: int, labels=None, lut=None, density=None, precision: int = F32,
-                       out: Inim | None = None) -> Inim:
+                       out: Inim | None = None, noalloc: bool = False) -> Inim:
+        """Step 4 through cg_integral_image, or through the allocation-free
+        cg_integral_image_noalloc when `noalloc` (inputs and `out` must then
+        already be device tensors for the call itself to allocate nothing)."""
         im = out or self.inim_alloc(N, precision)
         cim = im.c()
+        name = "cg_integral_image_noalloc" if noalloc else "cg_integral_image"
+        fn = getattr(lib(), name)
         if density is not None:
             dens = _dev(density, torch.float32, (N, N))
-            rc = lib().cg_integral_image(self.handle, int(N), None, None, 0, _ptr(dens), int(precision),
-                                         C.byref(cim), _stream())
+            rc = fn(self.handle, int(N), None, None, 0, _ptr(dens), int(precision), C.byref(cim), _stream())
         else:
             lab = labels if (isinstance(labels, torch.Tensor) and labels.is_cuda) else \
                 torch.as_tensor(np.asarray(labels).astype(np.uint16).view(np.int16)).cuda()
             lab = lab.contiguous()
             lt = _dev(lut, torch.float32)
-            rc = lib().cg_integral_image(self.handle, int(N), _ptr(lab), _ptr(lt), int(lt.numel()), None,
-                                         int(precision), C.byref(cim), _stream())
-        self._check(rc, "cg_integral_image")
+            rc = fn(self.handle, int(N), _ptr(lab), _ptr(lt), int(lt.numel()), None, int(precision), C.byref(cim),
+                    _stream())
+        self._check(rc, name)
         return im
 
     def map_points(self, im: Inim, xy_in, xy_out=None):

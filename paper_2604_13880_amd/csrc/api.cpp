@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -140,8 +141,26 @@ bool lut_fusable(const Plan& P) {
 
 int64_t pitch_of(int N) { return (int64_t)((N + 1 + 63) / 64) * 64; }
 
+// Caller-provided device memory for a plan (the allocation-free entry
+// point): scratch and descriptors are carved from it instead of the
+// context's grow-only buffers, and the descriptors are written by a kernel
+// from its arguments instead of a pinned staging copy.
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+};
+
+// Descriptor bytes written from kernel arguments (one block).
+constexpr int kBlobWords = 256;
+struct Blob {
+  uint32_t w[kBlobWords];
+};
+__global__ __launch_bounds__(256) void k_put_blob(uint32_t* dst, Blob b, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += 256) dst[i] = b.w[i];
+}
+
 int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int th, bool dense,
-               const Needs& nd, hipStream_t st, Plan& P, const char* tag) {
+               const Needs& nd, hipStream_t st, Plan& P, const char* tag, const Arena* arena = nullptr) {
   const int n = (int)specs.size();
   P.n = n;
   P.prec = prec;
@@ -243,13 +262,21 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     I.HB = s.HB;
     I.areas = s.areas;
   }
-  char* scratch = nullptr;
-  int rc = get_buf(c, (std::string(tag) + ":scratch").c_str(), std::max<size_t>(total, 256), st, &scratch);
-  if (rc) return rc;
+  char* ws = nullptr;
+  int rc = CG_OK;
+  if (arena) {
+    if (total > arena->bytes)
+      return fail(c, CG_EINVAL, "scratch of " + std::to_string(total) + " bytes exceeds the " +
+                                    std::to_string(arena->bytes) + "-byte static buffer");
+    ws = arena->base;
+  } else {
+    rc = get_buf(c, (std::string(tag) + ":scratch").c_str(), std::max<size_t>(total, 256), st, &ws);
+    if (rc) return rc;
+  }
   for (int k = 0; k < n; ++k) {
     Inst& I = P.inst[k];
     const Own& ow = owns[k];
-    char* b = scratch + base[k];
+    char* b = ws + base[k];
     auto at = [&](int64_t off) -> char* { return off >= 0 ? b + off : nullptr; };
     I.row_cnt = (uint32_t*)at(ow.rowcnt);
     I.xing = (uint64_t*)at(ow.xing);
@@ -314,8 +341,19 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
   const size_t tab_bytes = align_up(sizeof(uint32_t) * tab_words);
   const size_t st_bytes = align_up(sizeof(IterState) * n);
   char* desc = nullptr;
-  rc = get_buf(c, (std::string(tag) + ":desc").c_str(), inst_bytes + off_bytes + tab_bytes + st_bytes, st, &desc);
-  if (rc) return rc;
+  if (arena) {
+    const size_t at = align_up(total);
+    if (at + inst_bytes + off_bytes + tab_bytes + st_bytes > arena->bytes)
+      return fail(c, CG_EINVAL, "scratch and descriptors of " +
+                                    std::to_string(at + inst_bytes + off_bytes + tab_bytes + st_bytes) +
+                                    " bytes exceed the " + std::to_string(arena->bytes) + "-byte static buffer");
+    if (inst_bytes + off_bytes + tab_bytes > sizeof(Blob))
+      return fail(c, CG_EINVAL, "descriptors too large for an allocation-free call");
+    desc = arena->base + at;
+  } else {
+    rc = get_buf(c, (std::string(tag) + ":desc").c_str(), inst_bytes + off_bytes + tab_bytes + st_bytes, st, &desc);
+    if (rc) return rc;
+  }
   P.d_state = (IterState*)(desc + inst_bytes + off_bytes + tab_bytes);
   for (int k = 0; k < n; ++k) P.inst[k].st = P.d_state + k;
   std::vector<char> host(inst_bytes + off_bytes + tab_bytes, 0);
@@ -331,8 +369,16 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
         t[2 * b + 1] = (uint32_t)kind(kd)[k];
       }
   }
-  rc = upload(c, desc, host.data(), host.size(), st);
-  if (rc) return rc;
+  if (arena) {
+    Blob blob;
+    memset(&blob, 0, sizeof(blob));
+    memcpy(blob.w, host.data(), host.size());
+    hipLaunchKernelGGL(k_put_blob, dim3(1), dim3(256), 0, st, (uint32_t*)desc, blob,
+                       (int)((host.size() + 3) / 4));
+  } else {
+    rc = upload(c, desc, host.data(), host.size(), st);
+    if (rc) return rc;
+  }
   const int64_t* doff = (const int64_t*)(desc + inst_bytes);
   const uint32_t* dtab = (const uint32_t*)(desc + inst_bytes + off_bytes);
   Batch& B = P.B;
@@ -457,6 +503,87 @@ int check_launch(cg_ctx* c) {
 }  // namespace
 
 // ===========================================================================
+// Static device scratch of the allocation-free entry point
+// (cg_integral_image_noalloc).  Every GPU the library runs on holds its own
+// copy until the process ends.  Host code never uses the array's name as a
+// device address: cg_create looks up each device's copy once, with that
+// device current, and every later use goes through that address.
+
+constexpr size_t kNoAllocBytes = (size_t)24 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Called by cg_create with `device` current.
+void scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = p;
+  else (void)hipGetLastError();   // the entry point then reports CG_EDEVICE
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+int inim_args(cg_ctx* c, int N, const uint16_t* labels, const float* lut, int32_t n_lut, const float* density,
+              int precision, const cg_inim* out, const char* who) {
+  const std::string w(who);
+  if (!out || !out->S || !out->T || !out->HA || !out->HB) return fail(c, CG_EINVAL, w + ": output buffers missing");
+  if (!pow2_ok(N)) return fail(c, CG_EINVAL, w + ": N must be a power of two in [16, 8192]");
+  if (precision < CG_F32 || precision > CG_F64ACC) return fail(c, CG_EINVAL, w + ": bad precision");
+  if (!density && (!labels || !lut || n_lut < 1 || n_lut > 65536))
+    return fail(c, CG_EINVAL, w + ": need labels + lut (1 <= n_lut <= 65536) or a density texture");
+  if (((uintptr_t)labels | (uintptr_t)density) & 15)
+    return fail(c, CG_EINVAL, w + ": labels / density must be 16-byte aligned");
+  return CG_OK;
+}
+
+// One integral-image call: plan (from the context's buffers, or from
+// `arena`) and the launches of the three passes.
+int inim_run(cg_ctx* c, int N, const uint16_t* labels, const float* lut, int32_t n_lut, const float* density,
+             int precision, cg_inim* out, hipStream_t st, const Arena* arena) {
+  int tw, th;
+  shape_for(c, N, precision, (int64_t)N * N, &tw, &th);
+  cap_shape(N, &tw, &th);
+  Spec s;
+  s.N = N;
+  s.labels = (uint16_t*)labels;
+  s.lut = (float*)lut;
+  s.n_lut = n_lut;
+  s.density = density;
+  s.S = out->S;
+  s.T = out->T;
+  s.HA = out->HA;
+  s.HB = out->HB;
+  s.pitch = pitch_of(N);
+  Needs nd;
+  nd.sat = true;
+  Plan P;
+  int rc = build_plan(c, {s}, precision, tw, th, density != nullptr, nd, st, P, "call", arena);
+  if (rc) return rc;
+  P.B.skip_done = 0;
+  if (!cgk::launch_sat(P.B, precision, tw, th, density != nullptr, P.il, P.tiles, P.c1, P.c2, st, nullptr, nullptr))
+    return fail(c, CG_EUNSUPPORTED, "integral image: unsupported tile shape");
+  out->N = N;
+  out->precision = precision;
+  out->pitch = s.pitch;
+  return check_launch(c);
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 
 extern "C" {
@@ -469,6 +596,7 @@ int cg_create(int device, cg_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return CG_EDEVICE;
   cg_ctx* c = new cg_ctx();
   c->device = device;
+  scratch_lookup(device);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->pinned_ev, hipEventDisableTiming) != hipSuccess) {
     delete c;
@@ -618,41 +746,23 @@ int cg_inim_size(int N, int precision, int64_t* pitch, size_t* table_bytes, size
 int cg_integral_image(cg_ctx* c, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
                       const float* density, int precision, cg_inim* out, void* stream) {
   if (!c) return CG_EINVAL;
-  if (!out || !out->S || !out->T || !out->HA || !out->HB) return fail(c, CG_EINVAL, "cg_integral_image: output buffers missing");
-  if (!pow2_ok(N)) return fail(c, CG_EINVAL, "cg_integral_image: N must be a power of two in [16, 8192]");
-  if (precision < CG_F32 || precision > CG_F64ACC) return fail(c, CG_EINVAL, "cg_integral_image: bad precision");
-  if (!density && (!labels || !lut || n_lut < 1 || n_lut > 65536))
-    return fail(c, CG_EINVAL, "cg_integral_image: need labels + lut (1 <= n_lut <= 65536) or a density texture");
-  if (((uintptr_t)labels | (uintptr_t)density) & 15)
-    return fail(c, CG_EINVAL, "cg_integral_image: labels / density must be 16-byte aligned");
-  hipSetDevice(c->device);
-  hipStream_t st = pick_stream(c, stream);
-  int tw, th;
-  shape_for(c, N, precision, (int64_t)N * N, &tw, &th);
-  cap_shape(N, &tw, &th);
-  Spec s;
-  s.N = N;
-  s.labels = (uint16_t*)labels;
-  s.lut = (float*)lut;
-  s.n_lut = n_lut;
-  s.density = density;
-  s.S = out->S;
-  s.T = out->T;
-  s.HA = out->HA;
-  s.HB = out->HB;
-  s.pitch = pitch_of(N);
-  Needs nd;
-  nd.sat = true;
-  Plan P;
-  int rc = build_plan(c, {s}, precision, tw, th, density != nullptr, nd, st, P, "call");
+  int rc = inim_args(c, N, labels, lut, n_lut, density, precision, out, "cg_integral_image");
   if (rc) return rc;
-  P.B.skip_done = 0;
-  if (!cgk::launch_sat(P.B, precision, tw, th, density != nullptr, P.il, P.tiles, P.c1, P.c2, st, nullptr, nullptr))
-    return fail(c, CG_EUNSUPPORTED, "cg_integral_image: unsupported tile shape");
-  out->N = N;
-  out->precision = precision;
-  out->pitch = s.pitch;
-  return check_launch(c);
+  hipSetDevice(c->device);
+  return inim_run(c, N, labels, lut, n_lut, density, precision, out, pick_stream(c, stream), nullptr);
+}
+
+int cg_integral_image_noalloc(cg_ctx* c, int N, const uint16_t* labels, const float* lut, int32_t n_lut,
+                              const float* density, int precision, cg_inim* out, void* stream) {
+  if (!c) return CG_EINVAL;
+  int rc = inim_args(c, N, labels, lut, n_lut, density, precision, out, "cg_integral_image_noalloc");
+  if (rc) return rc;
+  Arena a;
+  a.base = (char*)scratch_ptr(c->device);
+  a.bytes = kNoAllocBytes;
+  if (!a.base) return fail(c, CG_EDEVICE, "cg_integral_image_noalloc: static scratch unavailable on this device");
+  hipSetDevice(c->device);
+  return inim_run(c, N, labels, lut, n_lut, density, precision, out, pick_stream(c, stream), &a);
 }
 
 int cg_map_points(cg_ctx* c, const cg_inim* im, const float* xy_in, float* xy_out, int64_t n_points,
