@@ -178,6 +178,45 @@ int cg_map_points(cg_ctx* ctx, const cg_inim* inim, const float* xy_in, float* x
 int cg_region_areas(cg_ctx* ctx, const cg_map* map, const float* xy, const float* values,
                     double* areas, double* eps_xi, void* stream);
 
+/* Geographic-distortion measures of a cartogram against its original map
+ * (Background, "Quality Measures"), from the label maps of the map and of
+ * the cartogram at the same texture size N (cg_rasterize, uint16 [N][N],
+ * 16-byte aligned) and the two position sets (float [n_vertices][2]):
+ *   adjacency: int64 [3]  |E_m|, |E_c|, |E_c n E_m|, where two regions are
+ *              neighbours when pixels of both share a pixel side (the
+ *              background, label 0, is no region);
+ *   overlap:   int64 [R+1] for every region v the largest |P_m n (P_c + t)|
+ *              over all translations t by whole pixels, P_m and P_c the
+ *              pixel sets of v in the two label maps ([0] = 0);
+ *   pixels:    int64 [2][R+1] |P_m|, then |P_c|, per region;
+ *   shape:     double [R+1] shape distortion of v: the symmetric
+ *              difference of P_m and the best-translated P_c over their
+ *              union, (|P_m| + |P_c| - 2 overlap) / (|P_m| + |P_c| - overlap)
+ *              (0 when both sets are empty, 1 when only one is; [0] = 0);
+ *   bary:      double [2][R+1][2] region barycentres (area centroids of
+ *              all of a region's rings) in the map, then in the cartogram,
+ *              or NULL;
+ *   summary:   double [4] topology distortion tau = 1 - |E_c n E_m| /
+ *              |E_c u E_m| (0 when both are empty), the mean and the max of
+ *              the shape distortion over regions 1..R, and the relative
+ *              position error R = sum over ordered pairs u != v of
+ *              |angle(b_c(u,v), b_m(u,v))| / (pi |V| (|V| - 1)), b(u,v) the
+ *              vector from u's barycentre to v's.
+ * Integer results are exact; the doubles are FP64 sums in a fixed order.
+ * 1 <= R <= 4095 (CG_EUNSUPPORTED otherwise); CG_EINVAL when a label map
+ * holds a label above R.  Blocking: returns when the results are written. */
+typedef struct {
+  int64_t* adjacency;
+  int64_t* overlap;
+  int64_t* pixels;
+  double* shape;
+  double* bary;
+  double* summary;
+} cg_quality_out;
+
+int cg_quality(cg_ctx* ctx, const cg_map* map, int N, const uint16_t* labels_map, const uint16_t* labels_cart,
+               const float* xy_map, const float* xy_cart, cg_quality_out* out, void* stream);
+
 /* Whole cartograms for time series (Method, Steps 0-7 iterated with the
  * stopping rule; "Coherence of Dynamic Cartograms" for the direct and
  * cumulative strategies).  One descriptor per series; every series has

@@ -46,6 +46,11 @@ class CgNetConfig(C.Structure):
                 ("in_channels", C.c_int32), ("residual_gain", C.c_float)]
 
 
+class CgQualityOut(C.Structure):
+    _fields_ = [("adjacency", C.c_void_p), ("overlap", C.c_void_p), ("pixels", C.c_void_p),
+                ("shape", C.c_void_p), ("bary", C.c_void_p), ("summary", C.c_void_p)]
+
+
 class CgSeriesOut(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("extra_xy", C.c_void_p), ("frames", C.c_void_p),
                 ("iters", C.c_void_p), ("status", C.c_void_p), ("flags", C.c_void_p),
@@ -77,6 +82,7 @@ def lib():
             "cg_integral_image_noalloc": (C.c_int, [vp, C.c_int, vp, vp, i32, vp, C.c_int, C.POINTER(CgInim), vp]),
             "cg_map_points": (C.c_int, [vp, C.POINTER(CgInim), vp, vp, i64, vp]),
             "cg_region_areas": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "cg_quality": (C.c_int, [vp, vp, C.c_int, vp, vp, vp, vp, C.POINTER(CgQualityOut), vp]),
             "cg_step_series": (C.c_int, [vp, C.POINTER(CgSeriesDesc), C.c_int, C.POINTER(CgSeriesOut), i32, vp]),
             "cg_tile_shape": (C.c_int, [vp, C.c_int, C.c_int, i64, C.POINTER(i32), C.POINTER(i32)]),
             "cg_autotune": (C.c_int, [vp, C.c_int, C.c_int, i32, C.c_char_p]),
@@ -112,7 +118,7 @@ def exported_symbols():
     return ["cg_create", "cg_destroy", "cg_last_error", "cg_stream", "cg_map_build", "cg_map_destroy",
             "cg_map_n_edges", "cg_rasterize", "cg_inim_size", "cg_integral_image", "cg_integral_image_noalloc",
             "cg_map_points",
-            "cg_region_areas", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
+            "cg_region_areas", "cg_quality", "cg_step_series", "cg_tile_shape", "cg_set_tile_shape", "cg_autotune", "cg_profile_stage",
             "cg_profile_read", "cg_log_density", "cg_log_density_maps", "cg_tracer_field", "cg_field_pool", "cg_net_create", "cg_net_destroy",
             "cg_net_n_params", "cg_net_get_params", "cg_net_set_params", "cg_net_get_grads", "cg_net_zero_grads",
             "cg_net_forward", "cg_net_backward", "cg_net_adam_step", "cg_net_save", "cg_net_load"]
@@ -282,6 +288,33 @@ class Context:
         rc = lib().cg_region_areas(self.handle, m.handle, _ptr(xy), _ptr(vals), _ptr(areas), _ptr(ex), _stream())
         self._check(rc, "cg_region_areas")
         return areas, ex
+
+    def quality(self, m: Map, N: int, xy_map, xy_cart, labels_map=None, labels_cart=None) -> dict:
+        """Geographic-distortion measures of the cartogram xy_cart against
+        the map xy_map (cg_quality), from their label maps at texture size N
+        (rasterised here through cg_rasterize when not given)."""
+        xm = _dev(xy_map, torch.float32, (-1, 2))
+        xc = _dev(xy_cart, torch.float32, (-1, 2))
+        if labels_map is None:
+            labels_map = self.rasterize(m, xm, N)[0]
+        if labels_cart is None:
+            labels_cart = self.rasterize(m, xc, N)[0]
+        R = m.n_regions
+        f64, i64 = torch.float64, torch.int64
+        out = dict(adjacency=torch.empty(3, dtype=i64, device="cuda"),
+                   overlap=torch.empty(R + 1, dtype=i64, device="cuda"),
+                   pixels=torch.empty((2, R + 1), dtype=i64, device="cuda"),
+                   shape=torch.empty(R + 1, dtype=f64, device="cuda"),
+                   bary=torch.empty((2, R + 1, 2), dtype=f64, device="cuda"),
+                   summary=torch.empty(4, dtype=f64, device="cuda"))
+        q = CgQualityOut(*[C.c_void_p(out[k].data_ptr()) for k in
+                           ("adjacency", "overlap", "pixels", "shape", "bary", "summary")])
+        rc = lib().cg_quality(self.handle, m.handle, int(N), _ptr(labels_map.contiguous()),
+                              _ptr(labels_cart.contiguous()), _ptr(xm), _ptr(xc), C.byref(q), _stream())
+        self._check(rc, "cg_quality")
+        s = out["summary"].cpu().numpy()
+        out.update(tau=float(s[0]), shape_mean=float(s[1]), shape_max=float(s[2]), rel_pos=float(s[3]))
+        return out
 
     def log_density(self, labels, counts, values, shape: float = 1.0):
         """log(d / mean d) of the Step-3 density from a label map and pixel counts."""

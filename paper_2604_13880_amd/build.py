@@ -27,7 +27,7 @@ FLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
-SOURCES = ["raster.hip", "sat.hip", "mapping.hip", "net.hip", "api.cpp", "net_api.cpp"]
+SOURCES = ["raster.hip", "sat.hip", "mapping.hip", "net.hip", "quality.hip", "api.cpp", "net_api.cpp"]
 
 
 def _compile(src: str) -> str:
