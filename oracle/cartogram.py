@@ -155,19 +155,42 @@ def rasterize(xy, ring_off, ring_idx, ring_reg, n_regions: int, N: int):
 # Step 3: density texture (reading R4)
 
 
-def density_lut(counts, values, b: float = 1.0, areas=None):
+def density_lut(counts, values, b: float = 1.0, areas=None, bg_mass=None):
     """LUT [R+1] of densities: lut[v] = s(v)/o(v), lut[0] = BDV = b*d0.
 
     With `areas` (polygon areas in pixel units) the density uses them in
-    place of the pixel counts (the POLYGON area source)."""
+    place of the pixel counts (the POLYGON area source).  With `bg_mass`
+    M_b (the background's share of the mass, eq.(4)) the BDV is
+    b * M_b / (background pixel count) instead, so that the background
+    holds the mass M_b (b * d0 when the raster has no background pixel)."""
     o = (np.asarray(counts, np.float64) if areas is None else np.asarray(areas, np.float64))[1:]
     s = np.asarray(values, np.float64)
     have = o > 0
     d0 = s[have].sum() / o.sum() if o.sum() > 0 else 1.0   # an empty raster: unit density
     lut = np.zeros(len(s) + 1)
     lut[1:][have] = s[have] / o[have]
-    lut[0] = b * d0
+    o_bg = float(counts[0])
+    lut[0] = b * (bg_mass / o_bg if (bg_mass is not None and o_bg > 0) else d0)
     return lut, d0
+
+
+def background_masses(series, area_min: float, area_max: float, t0: int = 0, t1: int | None = None, at=None):
+    """Background mass M_b(t) of every step of a value series [T][R] (the
+    time-varying section, eq.(4)): the map's total M_i(t) = sum_v s_t(v);
+    with M_min / M_max the extremes of M_i over the steps t0..t1,
+    w = (M_i(t) - M_min) / (M_max - M_min) (clamped to [0, 1] for steps
+    outside that range; 1 when M_max = M_min), the map's area fraction
+    A_i(t) = (1 - w) A_min + w A_max, and M_i / (M_i + M_b) = A_i gives
+    M_b(t) = M_i(t) (1 - A_i(t)) / A_i(t).  `at` evaluates the same rule
+    at other totals (the in-between frames of a series) with the extremes
+    still taken over the series' steps.  Returns (M_b, A_i)."""
+    S = np.asarray(series, np.float64)
+    t1 = S.shape[0] - 1 if t1 is None else t1
+    lo, hi = S.sum(axis=1)[t0:t1 + 1].min(), S.sum(axis=1)[t0:t1 + 1].max()
+    Mi = S.sum(axis=1) if at is None else np.asarray(at, np.float64)
+    w = np.ones_like(Mi) if hi == lo else np.clip((Mi - lo) / (hi - lo), 0.0, 1.0)
+    A = (1.0 - w) * area_min + w * area_max
+    return Mi * (1.0 - A) / A, A
 
 
 def density_texture(labels, lut):
@@ -420,7 +443,7 @@ class RunResult:
     extra: np.ndarray | None = None
 
 
-def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None):
+def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None, bg_mass=None):
     """One pass of Steps 2-6 on positions xy; returns the moved points and
     the intermediate products (labels, counts, lut, InIm, D, and the moved
     tracer points `extra` when given)."""
@@ -428,7 +451,7 @@ def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None):
     areas = None
     if area_source == "polygon":
         areas = region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions) * (N * N)
-    lut, _ = density_lut(counts, values, b, areas)
+    lut, _ = density_lut(counts, values, b, areas, bg_mass)
     d = density_texture(labels, lut)
     im = integral_images(d)
     Dx, Dy = displacement(im)
@@ -439,7 +462,7 @@ def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None):
 
 
 def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
-        area_source="pixel", fixed_iters=None, state_dtype=np.float64, extra=None) -> RunResult:
+        area_source="pixel", fixed_iters=None, state_dtype=np.float64, extra=None, bg_mass=None) -> RunResult:
     """Iterate until xi < tol, no new minimum in `patience` iterations, or
     max_iters (or exactly `fixed_iters` iterations when given).
 
@@ -470,7 +493,7 @@ def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
             if k >= max_iters:
                 status = STATUS_MAXITER
                 break
-        xy, info = iterate_once(xy, m, values, N, b, area_source, extra)
+        xy, info = iterate_once(xy, m, values, N, b, area_source, extra, bg_mass)
         xy = xy.astype(state_dtype).astype(np.float64)
         if extra is not None:
             extra = info["extra"].astype(state_dtype).astype(np.float64)
@@ -487,22 +510,48 @@ def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
 # time series (Method section, "Coherence of Dynamic Cartograms")
 
 
-def run_series(m, series, N, mode="direct", frames_per_step=0, **kw):
+def run_series(m, series, N, mode="direct", frames_per_step=0, frame_mode="positions", area_fraction=None, **kw):
     """Cartograms for every row of `series` [T][R].  Direct: every step
     deforms the original map; cumulative: every step starts from the
-    previous step's cartogram.  With frames_per_step = K > 0 the K-1
-    in-between frames of each transition are linear interpolations of the
-    vertex positions of consecutive steps."""
-    out = []
+    previous step's cartogram.  With frames_per_step = K > 0 each
+    transition gets K-1 in-between frames: frame_mode "positions" lerps
+    the vertex positions of consecutive steps; "values" computes a
+    cartogram of the lerped values (1 - k/K) s_t + (k/K) s_{t+1} for each
+    frame (from the original map in direct mode, from the previous frame
+    in cumulative mode, so that the chain runs step, frames, next step).
+    With area_fraction = (A_min, A_max[, t0, t1]) every step and frame
+    gets the background mass of eq.(4), the extremes of the map total
+    taken over the steps t0..t1 (all steps by default)."""
+    S = np.asarray(series, np.float64)
+    T = S.shape[0]
+    K = frames_per_step
+    by_values = K > 1 and frame_mode == "values"
+    if by_values:   # expanded series: step t at row t*K, frame k of transition t at row t*K + k
+        rows = [S[0]]
+        for t in range(1, T):
+            rows += [(1 - k / K) * S[t - 1] + (k / K) * S[t] for k in range(1, K)] + [S[t]]
+        E = np.stack(rows, 0)
+    else:
+        E = S
+    masses = [None] * E.shape[0]
+    if area_fraction is not None:
+        t0 = area_fraction[2] if len(area_fraction) > 2 else 0
+        t1 = area_fraction[3] if len(area_fraction) > 3 else T - 1
+        masses = list(background_masses(S, area_fraction[0], area_fraction[1], t0, t1, at=E.sum(axis=1))[0])
+    res_all = []
     prev = np.asarray(m.xy, np.float64)
-    for t in range(series.shape[0]):
+    for e in range(E.shape[0]):
         start = m.xy if mode == "direct" else prev
-        res = run(m, series[t], N, xy0=start, **kw)
-        out.append(res)
-        prev = res.xy
+        r = run(m, E[e], N, xy0=start, bg_mass=masses[e], **kw)
+        res_all.append(r)
+        prev = r.xy
+    if by_values:
+        out = [res_all[t * K] for t in range(T)]
+        frames = [np.stack([res_all[(t - 1) * K + k].xy for k in range(1, K)], 0) for t in range(1, T)]
+        return out, frames
+    out = res_all
     frames = []
-    if frames_per_step > 0:
-        K = frames_per_step
+    if K > 0:
         for t in range(1, len(out)):
             a, bq = out[t - 1].xy, out[t].xy
             frames.append(np.stack([a + (k / K) * (bq - a) for k in range(1, K)], 0))
