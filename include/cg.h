@@ -242,7 +242,26 @@ typedef struct {
   const float* init_field; /* warm start: float [G][G][2] displacement (dx, dy) at the pixel centres
                               ((i + 1/2)/G, (j + 1/2)/G) of a G x G grid, or NULL; see below */
   int32_t init_G;
+  /* Background mass from the map total (Method, "Interactive Steering",
+   * eq.(4)): with 0 < area_min <= area_max < 1, step t's background holds
+   * M_b(t) = M_i(t) (1 - A_i(t)) / A_i(t), M_i(t) the sum of its values,
+   * A_i(t) = (1 - w) area_min + w area_max, w = (M_i(t) - M_min) /
+   * (M_max - M_min) clamped to [0, 1] (1 when M_max = M_min), the extremes
+   * taken over steps mass_t0..mass_t1 (all steps when mass_t1 < mass_t0);
+   * the background density is shape * M_b / (background pixels).
+   * area_min = area_max = 0: off (background density shape * d0). */
+  float area_min;
+  float area_max;
+  int32_t mass_t0;
+  int32_t mass_t1;
+  int32_t frame_mode;   /* CG_FRAMES_POSITIONS / CG_FRAMES_VALUES, used when frames >= 2 */
 } cg_series_desc;
+
+/* In-between frames of a transition t-1 -> t (k = 1..K-1): */
+#define CG_FRAMES_POSITIONS 0 /* linear interpolation of the two steps' vertex positions */
+#define CG_FRAMES_VALUES 1    /* a cartogram of the values (1-k/K) s_{t-1} + (k/K) s_t, from the original
+                                 map (direct) or from the previous frame (cumulative: the chain runs step,
+                                 frames, next step); not with tracer points */
 
 typedef struct {
   float* xy;        /* device [T][n_vertices][2] */
@@ -254,6 +273,8 @@ typedef struct {
   double* eps;      /* HOST [T] final mean area error */
   double* xi;       /* HOST [T] final max area error */
   float* warm_step; /* HOST [T] warm-start step taken (0: plain start), or NULL */
+  int32_t* frame_iters; /* HOST [T-1][K-1] iterations of each CG_FRAMES_VALUES frame, or NULL */
+  double* frame_xi;     /* HOST [T-1][K-1] final max area error of each such frame, or NULL */
 } cg_series_out;
 
 /* Runs every series in desc[0..n_series); out[k] receives series k.

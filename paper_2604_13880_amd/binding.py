@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcg.so")
 
 F32, COMP, F64, F64ACC = 0, 1, 2, 3
 DIRECT, CUMULATIVE = 0, 1
+FRAMES_POSITIONS, FRAMES_VALUES = 0, 1
 AREA_PIXEL, AREA_POLYGON = 0, 1
 STATUS_CONVERGED, STATUS_STALLED, STATUS_MAXITER, STATUS_ERROR = 0, 1, 2, 3
 FLAG_CONTESTED, FLAG_OVERFLOW, FLAG_FALLBACK, FLAG_BADVALUES = 1, 2, 4, 8
@@ -37,7 +38,8 @@ class CgSeriesDesc(C.Structure):
                 ("area_source", C.c_int32), ("tol", C.c_float), ("patience", C.c_int32),
                 ("max_iters", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32),
                 ("frames", C.c_int32), ("extra", C.c_void_p), ("n_extra", C.c_int64),
-                ("init_field", C.c_void_p), ("init_G", C.c_int32)]
+                ("init_field", C.c_void_p), ("init_G", C.c_int32), ("area_min", C.c_float),
+                ("area_max", C.c_float), ("mass_t0", C.c_int32), ("mass_t1", C.c_int32), ("frame_mode", C.c_int32)]
 
 
 class CgNetConfig(C.Structure):
@@ -54,7 +56,8 @@ class CgQualityOut(C.Structure):
 class CgSeriesOut(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("extra_xy", C.c_void_p), ("frames", C.c_void_p),
                 ("iters", C.c_void_p), ("status", C.c_void_p), ("flags", C.c_void_p),
-                ("eps", C.c_void_p), ("xi", C.c_void_p), ("warm_step", C.c_void_p)]
+                ("eps", C.c_void_p), ("xi", C.c_void_p), ("warm_step", C.c_void_p),
+                ("frame_iters", C.c_void_p), ("frame_xi", C.c_void_p)]
 
 
 _lib = None
@@ -387,11 +390,13 @@ class Context:
     def step_series(self, series: list[dict], graph_iters: int = 8):
         """Run cartogram series.  Each dict: map (Map), xy0 (float32 [n,2]),
         N, values ([T,R] or [R]), and optional mode, shape, area_source,
-        tol, patience, max_iters, fixed_iters, precision, frames, extra
-        ([m,2] tracer points), init_field ([G,G,2] warm-start displacement at
-        pixel centres).  Returns one dict
-        per series with xy [T,n,2], extra_xy, frames, iters, status,
-        flags, eps, xi (host numpy for the scalars)."""
+        tol, patience, max_iters, fixed_iters, precision, frames, frame_mode
+        ("positions" or "values"), area_fraction ((A_min, A_max) or
+        (A_min, A_max, t0, t1): background mass of eq.(4)), extra ([m,2]
+        tracer points), init_field ([G,G,2] warm-start displacement at
+        pixel centres).  Returns one dict per series with xy [T,n,2],
+        extra_xy, frames, iters, status, flags, eps, xi (host numpy for the
+        scalars), and frame_iters / frame_xi [T-1,K-1] for value frames."""
         descs = (CgSeriesDesc * len(series))()
         outs = (CgSeriesOut * len(series))()
         keep, results = [], []
@@ -433,12 +438,25 @@ class Context:
             d.n_extra = 0 if extra is None else int(extra.shape[0])
             d.init_field = 0 if field is None else field.data_ptr()
             d.init_G = 0 if field is None else int(field.shape[0])
+            af = s.get("area_fraction")
+            if af is not None:
+                d.area_min, d.area_max = float(af[0]), float(af[1])
+                d.mass_t0, d.mass_t1 = (int(af[2]), int(af[3])) if len(af) > 2 else (0, -1)
+            else:
+                d.mass_t0, d.mass_t1 = 0, -1
+            fm = s.get("frame_mode", FRAMES_POSITIONS)
+            d.frame_mode = {"positions": FRAMES_POSITIONS, "values": FRAMES_VALUES}.get(fm, fm) \
+                if isinstance(fm, str) else int(fm)
+            if K >= 2 and d.frame_mode == FRAMES_VALUES:
+                host["frame_iters"] = np.zeros((max(T - 1, 0), K - 1), dtype=np.int32)
+                host["frame_xi"] = np.zeros((max(T - 1, 0), K - 1), dtype=np.float64)
             o = outs[k]
             o.xy = xy.data_ptr()
             o.extra_xy = 0 if exy is None else exy.data_ptr()
             o.frames = 0 if fr is None else fr.data_ptr()
-            for key in ("iters", "status", "flags", "eps", "xi", "warm_step"):
-                setattr(o, key, host[key].ctypes.data)
+            for key in ("iters", "status", "flags", "eps", "xi", "warm_step", "frame_iters", "frame_xi"):
+                if key in host:
+                    setattr(o, key, host[key].ctypes.data)
             keep += [vals, xy0, extra, field, xy, exy, fr]
             results.append(dict(xy=xy, extra_xy=exy, frames=fr, **host))
         rc = lib().cg_step_series(self.handle, descs, len(series), outs, int(graph_iters), _stream())

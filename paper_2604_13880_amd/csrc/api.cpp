@@ -104,6 +104,7 @@ struct Spec {
   int32_t area_source = CG_AREA_PIXEL, patience = 32, max_iters = 512, fixed_iters = 0;
   const float* init_field = nullptr;
   int64_t init_G = 0;
+  double bg_mass = -1.0;    // prescribed background mass (eq.(4)), < 0: shape * d0
 };
 
 struct Needs {
@@ -215,6 +216,7 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     I.fixed_iters = s.fixed_iters;
     I.shape = s.shape;
     I.tol = s.tol;
+    I.bg_mass = s.bg_mass;
     I.pitch = s.pitch ? s.pitch : pitch_of(N);
     I.xy = s.xy;
     I.extra = s.extra;
@@ -1046,8 +1048,11 @@ int cg_tile_shape(const cg_ctx* c, int N, int precision, int64_t batch_pixels, i
 
 namespace {
 
+// Where a cartogram's results go: time step `slot` >= 0, or value-
+// interpolated frame f = -1 - slot (transition t-1 -> t, frame k:
+// f = (t-1)(K-1) + k-1).
 struct StepRef {
-  int series, step;
+  int series, slot;
 };
 
 int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepRef>& refs,
@@ -1214,42 +1219,127 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
   for (int k = 0; k < n; ++k) {
     const StepRef& r = refs[k];
     cg_series_out& o = out[r.series];
-    if (o.iters) o.iters[r.step] = hs[k].iter;
-    if (o.status) o.status[r.step] = hs[k].status;
-    if (o.flags) o.flags[r.step] = hs[k].flags;
-    if (o.eps) o.eps[r.step] = hs[k].eps;
-    if (o.xi) o.xi[r.step] = hs[k].xi;
-    if (o.warm_step) o.warm_step[r.step] = hs[k].ws_alpha;
+    if (r.slot < 0) {
+      const int f = -1 - r.slot;
+      if (o.frame_iters) o.frame_iters[f] = hs[k].iter;
+      if (o.frame_xi) o.frame_xi[f] = hs[k].xi;
+      continue;
+    }
+    if (o.iters) o.iters[r.slot] = hs[k].iter;
+    if (o.status) o.status[r.slot] = hs[k].status;
+    if (o.flags) o.flags[r.slot] = hs[k].flags;
+    if (o.eps) o.eps[r.slot] = hs[k].eps;
+    if (o.xi) o.xi[r.slot] = hs[k].xi;
+    if (o.warm_step) o.warm_step[r.slot] = hs[k].ws_alpha;
   }
   (void)desc;
   return CG_OK;
 }
 
-Spec spec_for(const cg_series_desc& d, const cg_series_out& o, int t, bool cumulative) {
+// One cartogram of a series in the order its chain runs: a time step, or
+// (value-interpolated transitions) a frame between two steps.
+struct Link {
+  StepRef ref;
+  float* xy;             // output positions
+  float* extra;          // output tracer points or null
+  const float* values;   // [R] device
+  double bg_mass;        // eq.(4) background mass or -1
+  int prev;              // chain predecessor (cumulative start) or -1
+};
+
+Spec spec_for(const cg_series_desc& d, const std::vector<Link>& ch, int e, bool cumulative) {
   Spec s;
-  const int n = d.map->n_vert;
+  const Link& L = ch[e];
+  const bool chained = cumulative && L.prev >= 0;
   s.map = d.map;
   s.N = d.N;
-  s.xy = (float2*)(o.xy + (size_t)t * n * 2);
-  s.src_xy = (cumulative && t > 0) ? (const float2*)(o.xy + (size_t)(t - 1) * n * 2) : (const float2*)d.xy0;
-  if (d.extra && d.n_extra > 0 && o.extra_xy) {
-    s.extra = (float2*)(o.extra_xy + (size_t)t * d.n_extra * 2);
+  s.xy = (float2*)L.xy;
+  s.src_xy = chained ? (const float2*)ch[L.prev].xy : (const float2*)d.xy0;
+  if (L.extra) {
+    s.extra = (float2*)L.extra;
     s.n_extra = d.n_extra;
-    s.src_extra = (cumulative && t > 0) ? (const float2*)(o.extra_xy + (size_t)(t - 1) * d.n_extra * 2)
-                                        : (const float2*)d.extra;
+    s.src_extra = chained ? (const float2*)ch[L.prev].extra : (const float2*)d.extra;
   }
-  s.values = d.values + (size_t)t * d.map->R;
+  s.values = L.values;
+  s.bg_mass = L.bg_mass;
   s.shape = d.shape;
   s.tol = d.tol;
   s.area_source = d.area_source;
   s.patience = d.patience;
   s.max_iters = d.max_iters;
   s.fixed_iters = d.fixed_iters;
-  if (d.init_field && (!cumulative || t == 0)) {
+  if (d.init_field && (!cumulative || e == 0)) {
     s.init_field = d.init_field;
     s.init_G = d.init_G;
   }
   return s;
+}
+
+bool area_mode(const cg_series_desc& d) { return d.area_min != 0.f || d.area_max != 0.f; }
+bool value_frames(const cg_series_desc& d) { return d.frames >= 2 && d.frame_mode == CG_FRAMES_VALUES; }
+
+// The chain of cartograms of series d: its steps, with the value frames
+// between them when asked for (their values interpolated on the host into
+// `vbuf`, rows in chain order), and each one's background mass.
+int chain_for(cg_ctx* c, const cg_series_desc& d, const cg_series_out& o, int series, float* vbuf,
+              hipStream_t st, std::vector<Link>& ch) {
+  const int T = d.n_steps, R = d.map->R, K = d.frames;
+  const bool vf = value_frames(d);
+  const int64_t n = d.map->n_vert;
+  std::vector<float> hv;
+  std::vector<double> tot;
+  if (vf || area_mode(d)) {
+    hv.resize((size_t)T * R);
+    HIP_OK(c, hipMemcpyAsync(hv.data(), d.values, sizeof(float) * hv.size(), hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+  }
+  // chain order: step 0, (frames of transition 0 -> 1), step 1, ...
+  std::vector<float> ev;   // expanded values of the value frames, chain order
+  ch.clear();
+  for (int t = 0; t < T; ++t) {
+    if (vf && t > 0)
+      for (int k = 1; k < K; ++k) {
+        const int f = (t - 1) * (K - 1) + (k - 1);
+        Link L{{series, -1 - f}, o.frames + (size_t)f * n * 2, nullptr, nullptr, -1.0, (int)ch.size() - 1};
+        const double a = (double)k / K;
+        for (int v = 0; v < R; ++v)
+          ev.push_back((float)((1.0 - a) * hv[(size_t)(t - 1) * R + v] + a * hv[(size_t)t * R + v]));
+        L.values = vbuf + (ev.size() / R - 1) * R;
+        ch.push_back(L);
+      }
+    Link L{{series, t}, o.xy + (size_t)t * n * 2,
+           (d.extra && d.n_extra > 0 && o.extra_xy) ? o.extra_xy + (size_t)t * d.n_extra * 2 : nullptr,
+           d.values + (size_t)t * R, -1.0, (int)ch.size() - 1};
+    ch.push_back(L);
+  }
+  if (!ev.empty()) HIP_OK(c, hipMemcpyAsync(vbuf, ev.data(), sizeof(float) * ev.size(), hipMemcpyHostToDevice, st));
+  if (area_mode(d)) {
+    // eq.(4): map totals of the steps, their extremes over mass_t0..mass_t1
+    std::vector<double> M(T, 0.0);
+    for (int t = 0; t < T; ++t)
+      for (int v = 0; v < R; ++v) M[t] += (double)hv[(size_t)t * R + v];
+    const int t0 = d.mass_t1 >= d.mass_t0 ? d.mass_t0 : 0, t1 = d.mass_t1 >= d.mass_t0 ? d.mass_t1 : T - 1;
+    double lo = M[t0], hi = M[t0];
+    for (int t = t0; t <= t1; ++t) {
+      lo = std::min(lo, M[t]);
+      hi = std::max(hi, M[t]);
+    }
+    size_t fr = 0;
+    for (Link& L : ch) {
+      double Mi = 0.0;
+      if (L.ref.slot >= 0) {
+        Mi = M[L.ref.slot];
+      } else {
+        for (int v = 0; v < R; ++v) Mi += (double)ev[fr * R + v];
+        ++fr;
+      }
+      const double w = hi == lo ? 1.0 : std::min(1.0, std::max(0.0, (Mi - lo) / (hi - lo)));
+      const double A = (1.0 - w) * d.area_min + w * d.area_max;
+      L.bg_mass = Mi * (1.0 - A) / A;
+    }
+  }
+  if (!ev.empty()) HIP_OK(c, hipStreamSynchronize(st));   // ev is read by the copy above
+  return CG_OK;
 }
 
 }  // namespace
@@ -1258,6 +1348,7 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
                               int32_t graph_iters, void* stream) {
   if (!c) return CG_EINVAL;
   if (!desc || !out || n_series < 0) return fail(c, CG_EINVAL, "cg_step_series: bad arguments");
+  size_t vframes = 0;
   for (int i = 0; i < n_series; ++i) {
     const cg_series_desc& d = desc[i];
     if (!d.map || !d.xy0 || !d.values || !out[i].xy) return fail(c, CG_EINVAL, "cg_step_series: null map/xy0/values/out.xy");
@@ -1271,6 +1362,15 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
     if (d.frames >= 2 && !out[i].frames) return fail(c, CG_EINVAL, "cg_step_series: frames requested without a buffer");
     if (d.init_field && d.init_G < 1) return fail(c, CG_EINVAL, "cg_step_series: init_field needs init_G >= 1");
     if ((int64_t)d.map->n_vert + d.n_extra > INT32_MAX) return fail(c, CG_EINVAL, "cg_step_series: too many points");
+    if (d.frame_mode != CG_FRAMES_POSITIONS && d.frame_mode != CG_FRAMES_VALUES)
+      return fail(c, CG_EINVAL, "cg_step_series: bad frame mode");
+    if (value_frames(d) && d.extra && d.n_extra > 0)
+      return fail(c, CG_EUNSUPPORTED, "cg_step_series: value-interpolated frames with tracer points");
+    if (area_mode(d) && !(d.area_min > 0.f && d.area_min <= d.area_max && d.area_max < 1.f))
+      return fail(c, CG_EINVAL, "cg_step_series: need 0 < area_min <= area_max < 1");
+    if (area_mode(d) && d.mass_t1 >= d.mass_t0 && (d.mass_t0 < 0 || d.mass_t1 >= d.n_steps))
+      return fail(c, CG_EINVAL, "cg_step_series: mass_t0..mass_t1 outside the steps");
+    if (value_frames(d)) vframes += (size_t)(d.n_steps - 1) * (d.frames - 1) * d.map->R;
   }
   hipSetDevice(c->device);
   // order after the caller's stream, then run on the private (capturable) stream
@@ -1284,32 +1384,47 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
     HIP_OK(c, hipEventDestroy(ev));
   }
   c->last = st;
+  // value rows of the interpolated frames of every series
+  char* vb = nullptr;
+  if (vframes) {
+    int rc = get_buf(c, "series:frame_values", sizeof(float) * vframes, st, &vb);
+    if (rc) return rc;
+  }
+  std::vector<std::vector<Link>> chains(n_series);
+  {
+    size_t at = 0;
+    for (int i = 0; i < n_series; ++i) {
+      int rc = chain_for(c, desc[i], out[i], i, (float*)vb + at, st, chains[i]);
+      if (rc) return rc;
+      if (value_frames(desc[i])) at += (size_t)(desc[i].n_steps - 1) * (desc[i].frames - 1) * desc[i].map->R;
+    }
+  }
   for (int prec = CG_F32; prec <= CG_F64ACC; ++prec) {
-    // direct steps of every series with this precision: one batch
+    // direct cartograms of every series with this precision: one batch
     std::vector<Spec> specs;
     std::vector<StepRef> refs;
-    int max_t = 0;
+    size_t max_e = 0;
     for (int i = 0; i < n_series; ++i) {
       if (desc[i].precision != prec) continue;
       if (desc[i].mode == CG_DIRECT) {
-        for (int t = 0; t < desc[i].n_steps; ++t) {
-          specs.push_back(spec_for(desc[i], out[i], t, false));
-          refs.push_back({i, t});
+        for (size_t e = 0; e < chains[i].size(); ++e) {
+          specs.push_back(spec_for(desc[i], chains[i], (int)e, false));
+          refs.push_back(chains[i][e].ref);
         }
       } else {
-        max_t = std::max(max_t, desc[i].n_steps);
+        max_e = std::max(max_e, chains[i].size());
       }
     }
     int rc = run_batch(c, specs, refs, desc, out, prec, graph_iters, st);
     if (rc) return rc;
-    // cumulative series: step t of all of them together, in order
-    for (int t = 0; t < max_t; ++t) {
+    // cumulative series: link e of all of them together, in chain order
+    for (size_t e = 0; e < max_e; ++e) {
       specs.clear();
       refs.clear();
       for (int i = 0; i < n_series; ++i) {
-        if (desc[i].precision != prec || desc[i].mode != CG_CUMULATIVE || t >= desc[i].n_steps) continue;
-        specs.push_back(spec_for(desc[i], out[i], t, true));
-        refs.push_back({i, t});
+        if (desc[i].precision != prec || desc[i].mode != CG_CUMULATIVE || e >= chains[i].size()) continue;
+        specs.push_back(spec_for(desc[i], chains[i], (int)e, true));
+        refs.push_back(chains[i][e].ref);
       }
       rc = run_batch(c, specs, refs, desc, out, prec, graph_iters, st);
       if (rc) return rc;
@@ -1317,7 +1432,7 @@ extern "C" int cg_step_series(cg_ctx* c, const cg_series_desc* desc, int n_serie
   }
   for (int i = 0; i < n_series; ++i) {
     const cg_series_desc& d = desc[i];
-    if (d.frames < 2) continue;
+    if (d.frames < 2 || value_frames(d)) continue;
     const int64_t n = d.map->n_vert;
     for (int t = 1; t < d.n_steps; ++t)
       cgk::launch_frames(out[i].xy + (size_t)(t - 1) * n * 2, out[i].xy + (size_t)t * n * 2,

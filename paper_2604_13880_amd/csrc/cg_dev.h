@@ -69,6 +69,7 @@ struct InstT {
   int32_t area_source, patience, max_iters, fixed_iters;
   float shape, tol;
   int64_t pitch;
+  double bg_mass;                     // prescribed background mass M_b (eq.(4)), or < 0: BDV = shape * d0
   // topology
   typename PP::template p<const int4> edges;                  // (v0, v1, region A, region B)
   typename PP::template p<const int32_t> reg_pair_off;        // [R+1] region -> its ring edges
@@ -151,6 +152,14 @@ __device__ __forceinline__ int find_inst(const Batch& B, const int64_t* off, int
   lo = __builtin_amdgcn_readfirstlane(lo);
   first = off[lo];
   return lo;
+}
+
+// Background density of Step 3: shape * d0, or, with a prescribed
+// background mass M_b (eq.(4) of the steering section), shape * M_b / o_bg
+// so that the o_bg background pixels hold M_b (shape * d0 when there are none).
+template <typename I_>
+__device__ __forceinline__ double background_density(const I_& I, double d0, double o_bg) {
+  return (double)I.shape * ((I.bg_mass >= 0.0 && o_bg > 0.0) ? I.bg_mass / o_bg : d0);
 }
 
 // Descriptor k of a batch in registers (scalar loads; read-only in kernels).

@@ -28,7 +28,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 }
 
 // Step 3: density LUT.  d0 = sum s / sum o over map regions with o > 0,
-// background density b*d0; the LUT is scaled so the texture mass is N^2
+// background density b*d0 (or from a prescribed background mass); the LUT is scaled so the texture mass is N^2
 // (the map is invariant to a common scale of the density).
 __global__ __launch_bounds__(256) void k_density(Batch B) {
   int64_t first;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_density(Batch B) {
   ss = block_sum(ss, red);
   so = block_sum(so, red);
   const double d0 = so > 0.0 ? ss / so : 1.0;
-  const double bdv = (double)I.shape * d0;
+  const double bdv = background_density(I, d0, count(0));
   double cm = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
     const double o = poly ? I.areas[v] * NN : count(v);

@@ -346,8 +346,8 @@ __device__ __forceinline__ void acc_add_local<double, double>(double& a, double 
 // LUT in LDS from the pixel counts (or polygon areas) and the values, in
 // one fixed order, so all blocks hold the same table; the instance's first
 // block also publishes it (and d0, C) for the writer.  d0 = sum s / sum o
-// over regions with o > 0, background density shape * d0, LUT scaled so
-// the texture mass is N^2.
+// over regions with o > 0, background density shape * d0 (or from a
+// prescribed background mass), LUT scaled so the texture mass is N^2.
 template <int NT>
 __device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool publish) {
   constexpr int NW = NT / 64;
@@ -383,7 +383,7 @@ __device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool p
     sc += part[2][i];
   }
   const double d0 = so > 0.0 ? ss / so : 1.0;
-  const double bdv = (double)I.shape * d0;
+  const double bdv = background_density(I, d0, (double)I.counts[0]);
   const double cm = sc + bdv * (double)I.counts[0];
   const double kappa = cm > 0.0 ? NN / cm : 1.0;
   g_ptr<float> lut = (g_ptr<float>)I.lut;
