@@ -79,9 +79,14 @@ def _up(x):
     return x.repeat_interleave(2, dim=2).repeat_interleave(2, dim=3)
 
 
-def forward(p, x, c: int, L: int, out_scale: float, residual_gain: float = 0.0):
+def forward(p, x, c: int, L: int, out_scale: float, residual_gain: float = 0.0, store=None):
     """x: [B][H][W] or [B][H][W][C] -> (out [B][H][W][2], cache).  All
-    float64.  With a residual gain g the output adds g * x[..., 1:3]."""
+    float64.  With a residual gain g the output adds g * x[..., 1:3].
+
+    `store` (e.g. bf16_round) is applied where activations are stored
+    between layers: every ReLU output and every pooled input.  Without it
+    the pass is plain float64."""
+    sto = (lambda z: z) if store is None else (lambda z: torch.from_numpy(store(z.numpy())))
     xa = np.asarray(x, dtype=np.float64)
     if xa.ndim == 3:
         xa = xa[..., None]
@@ -93,10 +98,10 @@ def forward(p, x, c: int, L: int, out_scale: float, residual_gain: float = 0.0):
     src = t
     for l in range(L):
         if l > 0:
-            src = F.avg_pool2d(cache["e"][l - 1], 2)
+            src = sto(F.avg_pool2d(cache["e"][l - 1], 2))
         cache["in"].append(src)
-        a = torch.relu(F.conv2d(src, _w(p, layers[li]), _b(p, layers[li]), padding=1))
-        e = torch.relu(F.conv2d(a, _w(p, layers[li + 1]), _b(p, layers[li + 1]), padding=1))
+        a = sto(torch.relu(F.conv2d(src, _w(p, layers[li]), _b(p, layers[li]), padding=1)))
+        e = sto(torch.relu(F.conv2d(a, _w(p, layers[li + 1]), _b(p, layers[li + 1]), padding=1)))
         li += 2
         cache["a"].append(a)
         cache["e"].append(e)
@@ -106,8 +111,8 @@ def forward(p, x, c: int, L: int, out_scale: float, residual_gain: float = 0.0):
     cache["d"] = [None] * L
     for l in range(L - 2, -1, -1):
         cat = torch.cat([_up(deep), cache["e"][l]], dim=1)
-        da = torch.relu(F.conv2d(cat, _w(p, layers[li]), _b(p, layers[li]), padding=1))
-        d = torch.relu(F.conv2d(da, _w(p, layers[li + 1]), _b(p, layers[li + 1]), padding=1))
+        da = sto(torch.relu(F.conv2d(cat, _w(p, layers[li]), _b(p, layers[li]), padding=1)))
+        d = sto(torch.relu(F.conv2d(da, _w(p, layers[li + 1]), _b(p, layers[li + 1]), padding=1)))
         li += 2
         cache["cat"][l], cache["da"][l], cache["d"][l] = cat, da, d
         deep = d
@@ -134,8 +139,14 @@ def _conv_backward(g, inp, w):
     return dinp, dw, db
 
 
-def backward(p, cache, target, c: int, L: int, out_scale: float):
-    """Loss (mean squared error) and the flat gradient, float64."""
+def backward(p, cache, target, c: int, L: int, out_scale: float, store=None):
+    """Loss (mean squared error) and the flat gradient, float64.
+
+    `store` (e.g. bf16_round) is applied to the ReLU-masked output gradient
+    of every 3x3 layer before it enters the weight-gradient and
+    input-gradient products (the bias gradient sums it unrounded).  Without
+    it the pass is plain float64."""
+    sto = (lambda z: z) if store is None else (lambda z: torch.from_numpy(store(z.numpy())))
     layers, hw, hb, n = layer_table(c, L, cache["x"].shape[1])
     grads = np.zeros(n, dtype=np.float64)
     Wh = torch.from_numpy(np.asarray(p[hw:hw + 2 * c], dtype=np.float64)).reshape(2, c)
@@ -160,11 +171,11 @@ def backward(p, cache, target, c: int, L: int, out_scale: float):
     def conv_pair(g, ia, ib, inp, a, out_act):
         """Backward through out_act = relu(conv_b(a)), a = relu(conv_a(inp))."""
         g = g * (out_act > 0)
-        ga, dw, db = _conv_backward(g, a, _w(p, layers[ib]))
-        put(layers[ib], dw, db)
+        ga, dw, _ = _conv_backward(sto(g), a, _w(p, layers[ib]))
+        put(layers[ib], dw, g.sum(dim=(0, 2, 3)))
         ga = ga * (a > 0)
-        gi, dw, db = _conv_backward(ga, inp, _w(p, layers[ia]))
-        put(layers[ia], dw, db)
+        gi, dw, _ = _conv_backward(sto(ga), inp, _w(p, layers[ia]))
+        put(layers[ia], dw, ga.sum(dim=(0, 2, 3)))
         return gi
 
     g_skip = [None] * L

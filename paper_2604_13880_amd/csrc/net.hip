@@ -155,14 +155,16 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
 // Weight gradient dW[o][k] += sum_p g[p][o] * patch(in)[p][k].
 // Block: 32 output channels x 128 columns of K, 4 wavefronts each owning 32
 // columns; pixels in steps of 32 staged in LDS transposed ([channel][pixel]);
-// partial sums are added to the float32 gradient with atomics.
+// every block stores its partial sums for its share of the pixels
+// (blockIdx.z) in part[z][o][k]; k_sum_parts adds the shares to the
+// gradient in a fixed order, so the result does not depend on scheduling.
 constexpr int kWgPix = 32;
 constexpr int kWgPad = kWgPix + 8;   // row pitch in LDS (elements)
 
 template <bool GEN>
 __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict__ in, int Cin,
                                                      const uint16_t* __restrict__ g, int Cout,
-                                                     float* __restrict__ dW, int64_t P, int H, int W,
+                                                     float* __restrict__ part, int64_t P, int H, int W,
                                                      int64_t px_per_block) {
   __shared__ __align__(16) uint16_t As[32][kWgPad];    // g tile [o][pixel]
   __shared__ __align__(16) uint16_t Bs[128][kWgPad];   // patch tile [k][pixel]
@@ -243,6 +245,7 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
     }
   }
   // lane holds D[o = 4 kq + r][k = lr] of every fragment
+  float* dst = part + (int64_t)blockIdx.z * Cout * K;
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -252,9 +255,36 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = o0 + 16 * m + 4 * kq + r;
-        atomicAdd(dW + (int64_t)o * K + k, acc[m][f][r]);
+        dst[(int64_t)o * K + k] = acc[m][f][r];
       }
     }
+}
+
+// dst[i] += sum over z = 0..parts-1 of part[z][i], in that order.
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int64_t n, int parts,
+                                                   float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < parts; ++z) s += part[(int64_t)z * n + i];
+  dst[i] += s;
+}
+
+// dst[0] += sum over z of part[z] (FP64), fixed order: strided sums per
+// thread, then a fixed tree (one block).
+__global__ __launch_bounds__(256) void k_sum_parts_f64(const double* __restrict__ part, int parts,
+                                                       double* __restrict__ dst) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int z = t; z < parts; z += 256) s += part[z];
+  red[t] = s;
+  __syncthreads();
+  for (int d = 128; d >= 1; d >>= 1) {
+    if (t < d) red[t] += red[t + d];
+    __syncthreads();
+  }
+  if (t == 0) dst[0] += red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -371,9 +401,12 @@ __global__ __launch_bounds__(256) void k_skip_grad(const float* __restrict__ gca
   }
 }
 
-// bias gradient: db[c] += sum_p g[p][c]; block = 256 pixels-chunks x C channels
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ g, int C, int64_t P,
-                                                   int64_t px_per_block, float* __restrict__ db) {
+// bias gradient: block b stores sum over its pixels of the ReLU-masked
+// float32 gradient (g[p][c] where act[p][c] > 0) in part[b][c] (summed
+// into db by k_sum_parts).  It sums the float32 gradient, not its bfloat16
+// copy: a bias gradient is a sum over every pixel with much cancellation.
+__global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ g, const uint16_t* __restrict__ actv,
+                                                   int C, int64_t P, int64_t px_per_block, float* __restrict__ part) {
   __shared__ float red[256];
   const int t = threadIdx.x;
   const int lanes_per_px = C < 256 ? C : 256;   // C is 32, 64, 128 or a multiple of 256
@@ -385,12 +418,12 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
     const bool act = row < rows && c < C;
     float s = 0.f;
     if (act)
-      for (int64_t p = pbeg + row; p < pend; p += rows) s += bf2f(g[p * C + c]);
+      for (int64_t p = pbeg + row; p < pend; p += rows) s += bf2f(actv[p * C + c]) > 0.f ? g[p * C + c] : 0.f;
     red[t] = s;
     __syncthreads();
     if (row == 0 && act) {
       for (int r = 1; r < rows; ++r) s += red[r * lanes_per_px + t];
-      atomicAdd(db + c, s);
+      part[(int64_t)blockIdx.x * C + c] = s;
     }
     __syncthreads();
   }
@@ -427,11 +460,14 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* __restrict__ x
 // head's backward: gx[p][c] = sum_j go[p][j] w[j][c] (bfloat16),
 // dw[j][c] += sum_p go[p][j] x[p][c], db[j] += sum_p go[p][j],
 // go = scale * 2 (out - target) / (2 P).  loss[0] += sum (out - target)^2 / (2 P).
+// Block b stores its shares in part[b] = (dw [2][C], db [2]) and lpart[b]
+// (the loss), summed by k_sum_parts / k_sum_parts_f64 in a fixed order.
 __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x, int C, const float* __restrict__ w,
                                                   float scale, const float* __restrict__ out,
                                                   const float* __restrict__ target, int64_t P,
-                                                  float* __restrict__ gx, float* __restrict__ dw,
-                                                  float* __restrict__ db, double* __restrict__ loss) {
+                                                  float* __restrict__ gx, float* __restrict__ hpart,
+                                                  double* __restrict__ lpart) {
+  float* dw = hpart + (int64_t)blockIdx.x * (2 * C + 2);
   __shared__ float part[2][4][8];     // per-wave partial dw, 8 channels at a time
   __shared__ double lred[256];
   __shared__ float bred[2][256];
@@ -482,7 +518,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x
       const int j = t >> 3, e = t & 7;
       float s = 0.f;
       for (int q = 0; q < 4; ++q) s += part[j][q][e];
-      atomicAdd(dw + j * C + c + e, s);
+      dw[j * C + c + e] = s;
     }
     __syncthreads();
   }
@@ -495,9 +531,9 @@ __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* __restrict__ x
     __syncthreads();
   }
   if (t == 0) {
-    if (loss) atomicAdd(loss, lred[0]);
-    atomicAdd(db, bred[0][0]);
-    atomicAdd(db + 1, bred[1][0]);
+    lpart[blockIdx.x] = lred[0];
+    dw[2 * C] = bred[0][0];
+    dw[2 * C + 1] = bred[1][0];
   }
 }
 
@@ -569,23 +605,35 @@ void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* ou
   conv3_t<true>(in, Cin, wA, nullptr, out, Cout, Bn, H, W, 0, s);
 }
 
-void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, int Bn, int H, int W,
-                        hipStream_t s) {
-  const int64_t P = (int64_t)Bn * H * W;
+// Pixel shares of the weight gradient: enough to give the GPU ~4096
+// blocks, at least 256 pixels each.
+int64_t wgrad_splits(int64_t P, int Cin, int Cout, int64_t* px_per_block) {
   const int K = 9 * Cin;
-  const unsigned kt = (unsigned)((K + 127) / 128), ot = (unsigned)(Cout / 32);
-  // enough pixel splits to give the GPU ~4096 blocks, at least 256 pixels each
-  int64_t splits = 4096 / (int64_t)(kt * ot);
+  const int64_t kt = (K + 127) / 128, ot = Cout / 32;
+  int64_t splits = 4096 / (kt * ot);
   if (splits < 1) splits = 1;
   int64_t ppb = (P + splits - 1) / splits;
   if (ppb < 256) ppb = 256;
   ppb = (ppb + kWgPix - 1) / kWgPix * kWgPix;
-  splits = (P + ppb - 1) / ppb;
+  if (px_per_block) *px_per_block = ppb;
+  return (P + ppb - 1) / ppb;
+}
+
+// part: float [wgrad_splits(...)][Cout][9 Cin] scratch
+void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, float* part, int Bn,
+                        int H, int W, hipStream_t s) {
+  const int64_t P = (int64_t)Bn * H * W;
+  const int K = 9 * Cin;
+  const unsigned kt = (unsigned)((K + 127) / 128), ot = (unsigned)(Cout / 32);
+  int64_t ppb = 0;
+  const int64_t splits = wgrad_splits(P, Cin, Cout, &ppb);
   dim3 grid(kt, ot, (unsigned)splits);
   if (Cin % 8 == 0)
-    hipLaunchKernelGGL((k_conv3_wgrad<false>), grid, dim3(256), 0, s, in, Cin, g, Cout, dW, P, H, W, ppb);
+    hipLaunchKernelGGL((k_conv3_wgrad<false>), grid, dim3(256), 0, s, in, Cin, g, Cout, part, P, H, W, ppb);
   else
-    hipLaunchKernelGGL((k_conv3_wgrad<true>), grid, dim3(256), 0, s, in, Cin, g, Cout, dW, P, H, W, ppb);
+    hipLaunchKernelGGL((k_conv3_wgrad<true>), grid, dim3(256), 0, s, in, Cin, g, Cout, part, P, H, W, ppb);
+  const int64_t n = (int64_t)Cout * K;
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(n)), dim3(256), 0, s, part, n, (int)splits, dW);
 }
 
 void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s) {
@@ -611,20 +659,35 @@ void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, f
   hipLaunchKernelGGL(k_skip_grad, dim3(nblk((int64_t)Bn * H * W * (Cs / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gpool,
                      gskip, Cs, Bn, H, W);
 }
-void launch_bias_grad(const uint16_t* g, int C, int64_t P, float* db, hipStream_t s) {
+// Blocks of the bias gradient (at most 1024, at least 64 pixels each).
+int64_t bias_blocks(int64_t P, int64_t* px_per_block) {
   int64_t blocks = 1024;
   int64_t ppb = (P + blocks - 1) / blocks;
   if (ppb < 64) ppb = 64;
-  blocks = (P + ppb - 1) / ppb;
-  hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)blocks), dim3(256), 0, s, g, C, P, ppb, db);
+  if (px_per_block) *px_per_block = ppb;
+  return (P + ppb - 1) / ppb;
+}
+
+// g: float32 gradient of the layer's output, act: its stored activation;
+// part: float [bias_blocks(P)][C] scratch
+void launch_bias_grad(const float* g, const uint16_t* act, int C, int64_t P, float* db, float* part, hipStream_t s) {
+  int64_t ppb = 0;
+  const int64_t blocks = bias_blocks(P, &ppb);
+  hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)blocks), dim3(256), 0, s, g, act, C, P, ppb, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(C)), dim3(256), 0, s, part, (int64_t)C, (int)blocks, db);
 }
 void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, const float* resid,
                      int rc, float gain, float* out, int64_t P, hipStream_t s) {
   hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, b, scale, resid, rc, gain, out, P);
 }
+// part: float [nblk(P)][2C + 2] and lpart: double [nblk(P)] scratch; dw
+// and db are consecutive in the parameter layout (db = dw + 2C).
 void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, const float* out, const float* target,
-                     int64_t P, float* gx, float* dw, float* db, double* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P)), dim3(256), 0, s, x, C, w, scale, out, target, P, gx, dw, db, loss);
+                     int64_t P, float* gx, float* dw, double* loss, float* part, double* lpart, hipStream_t s) {
+  const unsigned blocks = nblk(P);
+  hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, x, C, w, scale, out, target, P, gx, part, lpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(2 * C + 2)), dim3(256), 0, s, part, (int64_t)(2 * C + 2), (int)blocks, dw);
+  if (loss) hipLaunchKernelGGL(k_sum_parts_f64, dim3(1), dim3(256), 0, s, lpart, (int)blocks, loss);
 }
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s) {

@@ -19,7 +19,9 @@ namespace cgn {
 bool conv3_supported(int Cin, int Cout);
 void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, uint16_t* out, int Cout, int Bn,
                   int H, int W, int relu, hipStream_t s);
-void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, int Bn, int H, int W,
+int64_t wgrad_splits(int64_t P, int Cin, int Cout, int64_t* px_per_block);
+int64_t bias_blocks(int64_t P, int64_t* px_per_block);
+void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout, float* dW, float* part, int Bn, int H, int W,
                         hipStream_t s);
 void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s);
 void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* out, int Cout, int Bn, int H, int W,
@@ -31,11 +33,11 @@ void launch_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, ui
 void launch_up_grad(const float* gcat, int Ccat, int Cd, float* gdeep, int Bn, int Ho, int Wo, hipStream_t s);
 void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, float* gskip, int Cs, int Bn,
                       int H, int W, hipStream_t s);
-void launch_bias_grad(const uint16_t* g, int C, int64_t P, float* db, hipStream_t s);
+void launch_bias_grad(const float* g, const uint16_t* act, int C, int64_t P, float* db, float* part, hipStream_t s);
 void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, const float* resid,
                      int rc, float gain, float* out, int64_t P, hipStream_t s);
 void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, const float* out, const float* target,
-                     int64_t P, float* gx, float* dw, float* db, double* loss, hipStream_t s);
+                     int64_t P, float* gx, float* dw, double* loss, float* part, double* lpart, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s);
 void launch_pack_w(const float* w, int Cin, int Cout, uint16_t* wA, uint16_t* wT, hipStream_t s);
@@ -77,6 +79,10 @@ struct cg_net {
   float *GA = nullptr, *GB = nullptr, *GC = nullptr;
   uint16_t* GM = nullptr;
   std::vector<float*> gskip;
+  // per-block shares of the parameter gradients and the loss, summed in a
+  // fixed order (the backward pass is deterministic)
+  float* part = nullptr;
+  double* lpart = nullptr;
 };
 
 namespace {
@@ -203,6 +209,20 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
     }
   }
   A(sizeof(float) * (size_t)B * n->H * n->W * 2, (void**)&n->out);
+  {
+    // largest share table of any layer at any batch up to max_batch
+    size_t parts = 0;
+    const int64_t hblocks = (B * n->H * n->W + 255) / 256;
+    parts = std::max(parts, (size_t)hblocks * (2 * c + 2));
+    for (const Conv& cv : n->conv)
+      for (int64_t b = 1; b <= B; ++b) {
+        const int64_t P = b * hl(n, cv.level) * wl(n, cv.level);
+        parts = std::max(parts, (size_t)cgn::wgrad_splits(P, cv.cin, cv.cout, nullptr) * cv.cout * 9 * cv.cin);
+        parts = std::max(parts, (size_t)cgn::bias_blocks(P, nullptr) * cv.cout);
+      }
+    A(sizeof(float) * parts, (void**)&n->part);
+    A(sizeof(double) * (size_t)hblocks, (void**)&n->lpart);
+  }
   A(2 * gmax, (void**)&n->GA);
   A(2 * gmax, (void**)&n->GB);
   A(2 * gmax, (void**)&n->GC);
@@ -338,7 +358,7 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
   // head: gradient of d_0 into GA
   const uint16_t* d0 = L >= 2 ? n->d_l[0] : n->e_l[0];
   cgn::launch_head_bwd(d0, n->c, n->params + n->head_w, n->cfg.out_scale, n->out, target, P0, n->GA,
-                       G + n->head_w, G + n->head_b, loss, st);
+                       G + n->head_w, loss, n->part, n->lpart, st);   // head_b follows head_w
   // decoder, from level 0 upwards; conv index of dec level l: 2L + 2 (L-2-l)
   for (int l = 0; l <= L - 2; ++l) {
     const int h = hl(n, l), w = wl(n, l);
@@ -347,13 +367,13 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
     const Conv& cb = n->conv[2 * L + 2 * (L - 2 - l) + 1];
     // d = relu(conv_b(da)); GA holds the gradient of d
     cgn::launch_relu_mask(n->GA, n->d_l[l], n->GM, P * cb.cout, st);
-    cgn::launch_conv3_wgrad(n->da_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GM, cb.cout, P, G + cb.b_off, st);
+    cgn::launch_conv3_wgrad(n->da_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, n->part, B, h, w, st);
+    cgn::launch_bias_grad(n->GA, n->d_l[l], cb.cout, P, G + cb.b_off, n->part, st);
     cgn::launch_conv3_f32(n->GM, cb.cout, cb.wT, n->GB, cb.cin, B, h, w, st);
     // da = relu(conv_a(cat))
     cgn::launch_relu_mask(n->GB, n->da_l[l], n->GM, P * ca.cout, st);
-    cgn::launch_conv3_wgrad(n->cat_l[l], ca.cin, n->GM, ca.cout, G + ca.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GM, ca.cout, P, G + ca.b_off, st);
+    cgn::launch_conv3_wgrad(n->cat_l[l], ca.cin, n->GM, ca.cout, G + ca.w_off, n->part, B, h, w, st);
+    cgn::launch_bias_grad(n->GB, n->da_l[l], ca.cout, P, G + ca.b_off, n->part, st);
     cgn::launch_conv3_f32(n->GM, ca.cout, ca.wT, n->GC, ca.cin, B, h, w, st);
     // cat = [up(deep), e_l]
     const int Cd = ch(n, l + 1), Cs = ch(n, l);
@@ -369,13 +389,13 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
     if (l < L - 1)  // e_l feeds the decoder skip and the pooled input of level l+1 (gradient in GC)
       cgn::launch_skip_grad(n->gskip[l], ch(n, l), 0, n->GC, n->GA, ch(n, l), B, h, w, st);
     cgn::launch_relu_mask(n->GA, n->e_l[l], n->GM, P * cb.cout, st);
-    cgn::launch_conv3_wgrad(n->a_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GM, cb.cout, P, G + cb.b_off, st);
+    cgn::launch_conv3_wgrad(n->a_l[l], cb.cin, n->GM, cb.cout, G + cb.w_off, n->part, B, h, w, st);
+    cgn::launch_bias_grad(n->GA, n->e_l[l], cb.cout, P, G + cb.b_off, n->part, st);
     cgn::launch_conv3_f32(n->GM, cb.cout, cb.wT, n->GB, cb.cin, B, h, w, st);
     cgn::launch_relu_mask(n->GB, n->a_l[l], n->GM, P * ca.cout, st);
     const uint16_t* src = l == 0 ? n->x_in : n->in_l[l];
-    cgn::launch_conv3_wgrad(src, ca.cin, n->GM, ca.cout, G + ca.w_off, B, h, w, st);
-    cgn::launch_bias_grad(n->GM, ca.cout, P, G + ca.b_off, st);
+    cgn::launch_conv3_wgrad(src, ca.cin, n->GM, ca.cout, G + ca.w_off, n->part, B, h, w, st);
+    cgn::launch_bias_grad(n->GB, n->a_l[l], ca.cout, P, G + ca.b_off, n->part, st);
     if (l > 0) cgn::launch_conv3_f32(n->GM, ca.cout, ca.wT, n->GC, ca.cin, B, h, w, st);
   }
   return check(n);

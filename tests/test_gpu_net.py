@@ -91,6 +91,79 @@ def test_forward_and_gradients_match_reference(ctx, L, H, W, B, cin, gain):
     net.close()
 
 
+def _maxrel(a, b):
+    """max |a - b| over the tensor's scale max |b| (element-wise check)."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def test_product_shape_elementwise(ctx):
+    """The shipped configuration: 4 levels, 32 base channels, 3 input
+    channels (log-density and a two-channel field), 128^2 grid, residual
+    head gain 2.4; batch 8 (the reference's float64 CPU pass stays within
+    seconds).
+
+    Bound, per tensor (output, every layer's weight and bias gradient, the
+    head), in relative norm and element-wise (max abs error over the
+    tensor's largest magnitude): the GPU may be no farther from the float64
+    net than the same float64 net with bfloat16 storage between layers
+    (unet.forward / backward with store=bf16_round) is, times 2, and never
+    beyond 3e-2 in norm / 6e-2 element-wise.  The storage roundings flip
+    ReLU masks near zero, and the gradients follow the masks
+    discontinuously, so two bfloat16 realisations differ from each other
+    about as much as either differs from float64 (measured: up to 2.5% in
+    norm at this shape).  A wrong element is off by the order of the
+    tensor's scale and fails the element-wise bound."""
+    import torch
+    from paper_2604_13880_amd import learned as Lr
+    cfg = Lr.NET_CFG
+    L, H, W, cin, gain = cfg["levels"], cfg["height"], cfg["width"], cfg["in_channels"], cfg["residual_gain"]
+    net, p, x, tgt = _setup(ctx, L, H, W, 8, seed=321, cin=cin, gain=gain)
+    q = _round_convs(p, C_BASE, L, cin)
+    got = net.forward(torch.from_numpy(x.astype(np.float32))).cpu().numpy()
+    net.zero_grads()
+    net.backward(torch.from_numpy(tgt.astype(np.float32)))
+    g = net.grads().cpu().numpy()
+    want, cache = unet.forward(q, x, C_BASE, L, SCALE, gain)
+    _, g_ref = unet.backward(q, cache, tgt, C_BASE, L, SCALE)
+    want16, cache16 = unet.forward(q, x, C_BASE, L, SCALE, gain, store=unet.bf16_round)
+    _, g16 = unet.backward(q, cache16, tgt, C_BASE, L, SCALE, store=unet.bf16_round)
+    layers, hw, hb, n = unet.layer_table(C_BASE, L, cin)
+    tensors = [("output", got, want, want16)]
+    for k, ly in enumerate(layers):
+        sw = slice(ly.w_off, ly.w_off + ly.cout * 9 * ly.cin)
+        sb = slice(ly.b_off, ly.b_off + ly.cout)
+        tensors.append((f"layer {k:2d} w ({ly.cin}->{ly.cout})", g[sw], g_ref[sw], g16[sw]))
+        tensors.append((f"layer {k:2d} b", g[sb], g_ref[sb], g16[sb]))
+    tensors.append(("head", g[hw:hb + 2], g_ref[hw:hb + 2], g16[hw:hb + 2]))
+    for name, a, ref, r16 in tensors:
+        en, ee = _rel(a, ref), _maxrel(a, ref)
+        sn, se = _rel(r16, ref), _maxrel(r16, ref)
+        print(f"{name:22s} gpu: norm {en:.2e} elem {ee:.2e} | bf16-storage net: norm {sn:.2e} elem {se:.2e}",
+              flush=True)
+        assert en <= min(3e-2, max(2 * sn, 5e-3)), name
+        assert ee <= min(6e-2, max(2 * se, 1e-2)), name
+    net.close()
+
+
+def test_backward_is_deterministic(ctx):
+    """Gradient shares are summed in a fixed order: two backward passes of
+    the same batch give the same bits (loss included)."""
+    import torch
+    net, p, x, tgt = _setup(ctx, 3, 64, 64, 4, seed=11, cin=3, gain=1.0)
+    xt = torch.from_numpy(x.astype(np.float32))
+    tt = torch.from_numpy(tgt.astype(np.float32))
+    out = []
+    for _ in range(2):
+        net.forward(xt)
+        net.zero_grads()
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        net.backward(tt, loss)
+        out.append((net.grads().clone(), loss.clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    net.close()
+
+
 def test_gradients_accumulate_and_reset(ctx):
     import torch
     net, p, x, tgt = _setup(ctx, 2, 32, 32, 1, seed=7)

@@ -105,3 +105,27 @@ def test_adam_first_step_moves_by_lr_times_sign():
     q, m, v = unet.adam(p, g, np.zeros(3), np.zeros(3), 1, lr=0.1, eps=1e-12)
     # after one bias-corrected step m_hat = g, v_hat = g^2: the move is lr * sign(g)
     assert np.allclose(q, [0.9, -1.9, 3.0], atol=1e-9)
+
+
+def test_storage_rounding_option():
+    """store=bf16_round rounds exactly the stored activations (every one a
+    bfloat16 value) and the masked gradients entering the products; with
+    store=None the pass is the plain float64 one (the finite-difference
+    pins above)."""
+    c, L = 8, 2
+    rng = np.random.default_rng(4)
+    p = unet.init_params(c, L, 4, cin0=2) + 0.02 * rng.standard_normal(unet.layer_table(c, L, 2)[3])
+    x = unet.bf16_round(rng.standard_normal((2, 8, 8, 2)))
+    tgt = 0.1 * rng.standard_normal((2, 8, 8, 2))
+    o1, c1 = unet.forward(p, x, c, L, 0.2, 0.5)
+    o2, c2 = unet.forward(p, x, c, L, 0.2, 0.5, store=lambda z: z)
+    assert np.array_equal(o1, o2)
+    o3, c3 = unet.forward(p, x, c, L, 0.2, 0.5, store=unet.bf16_round)
+    for key in ("a", "e"):
+        for t in c3[key]:
+            v = t.numpy()
+            assert np.array_equal(v, unet.bf16_round(v))
+    assert 0 < np.abs(o3 - o1).max() < 1e-2 * np.abs(o1).max()
+    l1, g1 = unet.backward(p, c1, tgt, c, L, 0.2)
+    l2, g2 = unet.backward(p, c1, tgt, c, L, 0.2, store=lambda z: z)
+    assert l1 == l2 and np.array_equal(g1, g2)
