@@ -98,6 +98,8 @@ void* cg_stream(const cg_ctx* ctx);
 int cg_map_build(cg_ctx* ctx, int32_t n_vertices, int32_t n_regions, int32_t n_rings,
                  const int32_t* ring_off, const int32_t* ring_idx, const int32_t* ring_reg,
                  cg_map** out);
+/* Frees the map's device buffers; the map may outlive the context that
+ * built it (destroying it after cg_destroy is fine). */
 int cg_map_destroy(cg_map* map);
 int32_t cg_map_n_edges(const cg_map* map);
 

@@ -676,7 +676,7 @@ int cg_map_build(cg_ctx* c, int32_t n_vertices, int32_t n_regions, int32_t n_rin
     }
   }
   cg_map* m = new cg_map();
-  m->ctx = c;
+  m->device = c->device;
   m->n_vert = n_vertices;
   m->R = n_regions;
   m->n_rings = n_rings;
@@ -700,8 +700,10 @@ int cg_map_build(cg_ctx* c, int32_t n_vertices, int32_t n_regions, int32_t n_rin
 
 int cg_map_destroy(cg_map* m) {
   if (!m) return CG_EINVAL;
-  if (m->ctx) hipSetDevice(m->ctx->device);
-  hipDeviceSynchronize();
+  // the map owns its buffers and records its device: destroying it after
+  // its context is fine
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
   hipFree(m->d_edges);
   hipFree(m->d_reg_pair_off);
   hipFree(m->d_reg_pairs);

@@ -26,7 +26,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 }  // namespace cgh
 
 struct cg_map {
-  cg_ctx* ctx = nullptr;
+  int device = 0;            // HIP device holding the map (the map may outlive its context)
   int32_t n_vert = 0, R = 0, n_rings = 0, n_edges = 0;
   int4* d_edges = nullptr;
   int32_t* d_reg_pair_off = nullptr;   // [R+1] region -> its ring edges

@@ -73,14 +73,26 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
     const int64_t dy = by - ay, dx = bx - ax;
     const int64_t den = (int64_t)kSub * dy;
     const uint64_t regs = ((uint64_t)(uint16_t)E[j].z << 16) | ((uint64_t)(uint16_t)E[j].w << 32);
-    for (int q = q0; q < q1; ++q) {
-      const int64_t yc = (int64_t)kSub * q + kSub / 2;
-      // centre p is at or right of the crossing iff 256 p dy >= num
-      const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
-      int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
-      if (p0 > N) p0 = N;
-      const uint32_t slot = g_atomic_add(&I.row_cnt[q], 1u);   // a full bucket is the fill's overflow
-      if (slot < (uint32_t)kFillXing) I.xing[(int64_t)q * kFillXing + slot] = (uint64_t)p0 | regs;
+    // rows in groups of 8: the group's slot claims are all in flight before
+    // the first one is used (a stretched edge crosses many rows, and one
+    // claim at a time made its thread the launch's longest chain)
+    for (int qb = q0; qb < q1; qb += 8) {
+      uint32_t slot[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        slot[u] = qb + u < q1 ? g_atomic_add(&I.row_cnt[qb + u], 1u) : (uint32_t)kFillXing;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = qb + u;
+        if (q >= q1) break;
+        const int64_t yc = (int64_t)kSub * q + kSub / 2;
+        // centre p is at or right of the crossing iff 256 p dy >= num
+        const int64_t num = (yc - ay) * dx - ((int64_t)(kSub / 2) - ax) * dy;
+        int64_t p0 = num <= 0 ? 0 : (num + den - 1) / den;
+        if (p0 > N) p0 = N;
+        // a full bucket is the fill's overflow
+        if (slot[u] < (uint32_t)kFillXing) I.xing[(int64_t)q * kFillXing + slot[u]] = (uint64_t)p0 | regs;
+      }
     }
   }
 }
@@ -175,6 +187,41 @@ __device__ __forceinline__ uint32_t bitonic_sort(uint32_t key, int lane) {
   return key;
 }
 
+// Cross-lane moves by DPP (no LDS traffic).  wave_shr1: lane l reads lane
+// l-1 (lane 0 reads `edge`); wave_shl1: lane l reads lane l+1 (lane 63
+// reads `edge`).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t edge) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_shl1(uint32_t v, uint32_t edge) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xf, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+// Inclusive xor / sum scans over the wavefront: row shifts 1, 2, 4, 8, then
+// row 0's total into row 1 and row 2's into row 3, then lane 31's into
+// rows 2 and 3 (lanes whose source lies outside the row read 0).
+__device__ __forceinline__ uint32_t wave_xor_scan(uint32_t x) {
+  x ^= dpp_u32<0x111, 0xf>(x);
+  x ^= dpp_u32<0x112, 0xf>(x);
+  x ^= dpp_u32<0x114, 0xf>(x);
+  x ^= dpp_u32<0x118, 0xf>(x);
+  x ^= dpp_u32<0x142, 0xa>(x);
+  x ^= dpp_u32<0x143, 0xc>(x);
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_add_scan(uint32_t x) {
+  x += dpp_u32<0x111, 0xf>(x);
+  x += dpp_u32<0x112, 0xf>(x);
+  x += dpp_u32<0x114, 0xf>(x);
+  x += dpp_u32<0x118, 0xf>(x);
+  x += dpp_u32<0x142, 0xa>(x);
+  x += dpp_u32<0x143, 0xc>(x);
+  return x;
+}
+
 // One wavefront per row.  Crossings sorted by p0; t = A xor B for every
 // crossing; the inclusive xor-scan X gives the claiming region after every
 // prefix as long as at most one region claims (the claim set starts empty
@@ -193,6 +240,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   __shared__ uint16_t sp_start[4][kFillXing + 2];
   __shared__ uint16_t sp_lab[4][kFillXing + 2];
   __shared__ uint32_t lcount[kLutLds];
+  __shared__ uint32_t rbits[4][kLutLds / 32];   // regions of a row (exact claim sets)
   __shared__ unsigned long long contested_blk;
   const int N = I.N, R = I.R;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -215,102 +263,101 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
     }
     __syncthreads();
-    if (row_ok && cnt <= 64) {
-      // bitonic sort of 32-bit keys (p0, slot) over the smallest power of
-      // two of lanes that holds the row's crossings; the record follows
-      // from the slot
-      const uint32_t key0 = lane < (int)cnt ? (((uint32_t)(xs[w][lane] & 0xFFFFull) << 6) | (uint32_t)lane) : ~0u;
-      uint32_t key;
-      if (cnt <= 2) key = bitonic_sort<2>(key0, lane);
-      else if (cnt <= 4) key = bitonic_sort<4>(key0, lane);
-      else if (cnt <= 8) key = bitonic_sort<8>(key0, lane);
-      else if (cnt <= 16) key = bitonic_sort<16>(key0, lane);
-      else if (cnt <= 32) key = bitonic_sort<32>(key0, lane);
-      else key = bitonic_sort<64>(key0, lane);
-      if (lane < (int)cnt) srt[w][lane] = xs[w][key & 63u];
-    } else if (row_ok) {  // rank sort by (p0, slot)
-      for (uint32_t i = lane; i < cnt; i += 64) {
-        const uint64_t a = xs[w][i];
-        const uint32_t pa = (uint32_t)(a & 0xFFFFu);
+    cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)cnt);   // one row per wavefront
+    if (row_ok) {
+      // rank sort by the keys (p0, slot): every key is compared with all
+      // others, read by lane (rows up to 64 crossings) or as LDS
+      // broadcasts (longer rows, up to four keys per lane)
+      if (cnt <= 64) {
+        const uint64_t rec = lane < (int)cnt ? xs[w][lane] : 0ull;
+        const uint32_t key = lane < (int)cnt ? (((uint32_t)(rec & 0xFFFFull) << 8) | (uint32_t)lane) : ~0u;
         uint32_t rank = 0;
-        for (uint32_t j = 0; j < cnt; ++j) {
-          const uint32_t pj = (uint32_t)(xs[w][j] & 0xFFFFu);
-          rank += (pj < pa) || (pj == pa && j < i);
+        for (uint32_t j = 0; j < cnt; ++j) rank += (uint32_t)__builtin_amdgcn_readlane((int)key, (int)j) < key;
+        if (lane < (int)cnt) srt[w][rank] = rec;
+      } else {
+        uint32_t key[4], rank[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const uint32_t i = (uint32_t)(lane + 64 * m);
+          key[m] = i < cnt ? (((uint32_t)(xs[w][i] & 0xFFFFull) << 8) | i) : ~0u;
         }
-        srt[w][rank] = a;
+        for (uint32_t j = 0; j < cnt; ++j) {
+          const uint32_t kj = ((uint32_t)(xs[w][j] & 0xFFFFull) << 8) | j;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) rank[m] += kj < key[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if ((uint32_t)(lane + 64 * m) < cnt) srt[w][rank[m]] = xs[w][lane + 64 * m];
       }
     }
     __syncthreads();
     if (row_ok) {
     uint32_t ngroups = 0;
+    bool serial = false;     // the exact serial walk decides the row
     if (cnt <= 64) {
       // one crossing per lane, sorted by p0
       const bool live = lane < (int)cnt;
       const uint64_t rec = live ? srt[w][lane] : 0ull;
       const uint32_t p0 = (uint32_t)(rec & 0xFFFFu);
       const uint32_t ra = (uint32_t)((rec >> 16) & 0xFFFFu), rb = (uint32_t)((rec >> 32) & 0xFFFFu);
-      const uint32_t pnext = __shfl_down(p0, 1, 64);
+      const uint32_t pnext = wave_shl1(p0, 0u);
       const bool last = live && (lane + 1 == (int)cnt || pnext != p0);
-      uint32_t x = live ? (ra ^ rb) : 0u;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x ^= y;
-      }
-      // the lane ending a group of crossings at one p0 replays that group
-      // on the claim set before it ({xb}, or empty when xb = 0): the xor
-      // labels stay exact iff at most one region claims afterwards
+      const uint32_t x = wave_xor_scan(live ? (ra ^ rb) : 0u);
+      // every group a single crossing: the claim set before it is {xb}
+      // (empty when xb = 0), after it the odd-multiplicity members of
+      // {xb, ra, rb}; the xor label is exact iff at most one remains.  Rows
+      // with several crossings at one p0 (a boundary wiggling inside one
+      // pixel: most rows of fractal maps) take the exact claim sets below.
       bool ok = !bad;
-      const uint32_t pprev = __shfl_up(p0, 1, 64);
+      const uint32_t pprev = wave_shr1(p0, 0u);
       const bool first = live && (lane == 0 || pprev != p0);
       if (__all(!last || first)) {
-        // every group is a single crossing: the claim set before it is {xb}
-        // (empty when xb = 0), after it the odd-multiplicity members of
-        // {xb, ra, rb}; the xor label is exact iff at most one remains
         if (last) ok = ok && single_claim_ok(x ^ ra ^ rb, ra, rb);
-      } else if (last) {
-        uint32_t xb = x;
-        int j = lane, members = 0;
-        while (true) {
-          const uint64_t rj = srt[w][j];
-          xb ^= (uint32_t)((rj >> 16) & 0xFFFFu) ^ (uint32_t)((rj >> 32) & 0xFFFFu);
-          ++members;
-          if (j == 0 || (uint32_t)(srt[w][j - 1] & 0xFFFFu) != p0 || members > kSetCap) break;
-          --j;
-        }
-        if (members > kSetCap) {
-          ok = false;
-        } else {
-          Claims cl;
-          cl.cur = (int)xb;
-          cl.multi = false;
-#pragma unroll
-          for (int i = 0; i < kSetCap; ++i) cl.set[i] = 0;
-          bool over = false;
-          for (int i = j; i <= lane; ++i) {
-            const uint64_t ri = srt[w][i];
-            claims_toggle(cl, (int)((ri >> 16) & 0xFFFFu), over);
-            claims_toggle(cl, (int)((ri >> 32) & 0xFFFFu), over);
-          }
-          int lab, n;
-          claims_label(cl, lab, n);
-          ok = ok && !over && n <= 1 && (uint32_t)lab == x;
-        }
+      } else {
+        ok = false;
       }
       uint32_t label = x, nclaim = x != 0u;
-      if (__any(!ok)) {
-        // exact claim sets in parallel: for every distinct region of the row,
-        // its parity after crossing k is the parity of the crossings <= k
-        // that toggle it
+      if (__any(!ok) && lds_counts) {
+        // exact claim sets in parallel: for every distinct region v of the
+        // row (from a bitmap of the row's regions), its parity after
+        // crossing k is the parity of the crossings <= k that toggle it
+        // (an edge with v on one side only)
+        label = 0u;
+        nclaim = 0u;
+        const uint64_t upto = (2ull << lane) - 1ull;
+        if (lane < kLutLds / 32) rbits[w][lane] = 0u;
+        if (live) {
+          if (ra) atomicOr(&rbits[w][ra >> 5], 1u << (ra & 31u));
+          if (rb) atomicOr(&rbits[w][rb >> 5], 1u << (rb & 31u));
+        }
+        const int nwords = (R + 32) >> 5;       // words holding ids 0..R
+        for (int wi = 0; wi < nwords; ++wi) {
+          uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)rbits[w][wi]);
+          while (bits) {
+            const uint32_t v = (uint32_t)wi * 32u + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1u;
+            const uint64_t mv = __ballot(live && ((ra == v) != (rb == v)));
+            if (live && (__popcll(mv & upto) & 1)) {
+              ++nclaim;
+              label = max(label, v);
+            }
+          }
+        }
+      } else if (__any(!ok)) {
+        // the same without the bitmap (more regions than it holds)
         label = 0u;
         nclaim = 0u;
         const uint64_t upto = (2ull << lane) - 1ull;
         for (int j = 0; j < (int)cnt; ++j) {
+          const uint32_t raj = (uint32_t)__builtin_amdgcn_readlane((int)ra, j);
+          const uint32_t rbj = (uint32_t)__builtin_amdgcn_readlane((int)rb, j);
           for (int side = 0; side < 2; ++side) {
-            const uint32_t v = (uint32_t)__shfl((int)(side ? rb : ra), j, 64);
+            const uint32_t v = side ? rbj : raj;
             if (v == 0u) continue;
-            const uint64_t m = __ballot(live && (ra == v || rb == v));
-            if ((int)(__ffsll((long long)m) - 1) < j || (side == 1 && (uint32_t)__shfl((int)ra, j, 64) == v)) continue;
+            const uint64_t seen = __ballot(live && (ra == v || rb == v));
+            if ((int)(__ffsll((long long)seen) - 1) < j || (side == 1 && raj == v)) continue;
+            const uint64_t m = __ballot(live && ((ra == v) != (rb == v)));
             if (live && (__popcll(m & upto) & 1)) {
               ++nclaim;
               label = max(label, v);
@@ -341,17 +388,145 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
           else g_atomic_add((g_ptr<unsigned long long>)&I.counts[0], (unsigned long long)first);
         }
       }
-      for (int d = 32; d >= 1; d >>= 1) cont += __shfl_xor(cont, d, 64);
-      if (lane == 0) {
-        if (cont) {
+      if (__any(cont != 0ull)) {
+        for (int d = 32; d >= 1; d >>= 1) cont += __shfl_xor(cont, d, 64);
+        if (lane == 0) {
           atomicAdd(&contested_blk, cont);
           g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_CONTESTED);
         }
-        if (bad) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
       }
+      if (lane == 0 && bad) g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_OVERFLOW);
       ngroups = __popcll(lastmask);
-    } else if (lane == 0) {
-      // long rows: exact serial walk of the claim set
+    } else {
+      // long rows: four consecutive sorted crossings i = 4 lane + m per
+      // lane; the same xor labels and single-claim test as above, on every
+      // crossing alone at its p0 (rows with coincident crossings, or whose
+      // test fails, take the serial walk)
+      uint32_t p[4], ra[4], rb[4], lx[4];
+      bool live[4];
+      uint32_t acc = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t i = 4 * (uint32_t)lane + m;
+        live[m] = i < cnt;
+        const uint64_t rec = live[m] ? srt[w][i] : 0ull;
+        p[m] = (uint32_t)(rec & 0xFFFFu);
+        ra[m] = (uint32_t)((rec >> 16) & 0xFFFFu);
+        rb[m] = (uint32_t)((rec >> 32) & 0xFFFFu);
+        acc ^= live[m] ? (ra[m] ^ rb[m]) : 0u;
+        lx[m] = acc;
+      }
+      const uint32_t xin = wave_xor_scan(acc);
+      const uint32_t xex = xin ^ acc;                  // xor of the crossings of the lanes before
+      const uint32_t pbefore = wave_shr1(p[3], 0u);    // p0 of crossing 4 lane - 1
+      const uint32_t pafter = wave_shl1(p[0], 0u);     // p0 of crossing 4 lane + 4
+      bool single = true, ok = true;
+      uint32_t nlast = 0;
+      bool last[4];
+      uint32_t x[4], pn[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t i = 4 * (uint32_t)lane + m;
+        x[m] = xex ^ lx[m];
+        const uint32_t pv = m == 0 ? pbefore : p[m - 1];
+        pn[m] = m == 3 ? pafter : p[m + 1];
+        const bool has_next = i + 1 < cnt;
+        last[m] = live[m] && (!has_next || pn[m] != p[m]);
+        const bool first = live[m] && (i == 0 || pv != p[m]);
+        single = single && (!live[m] || (last[m] && first));
+        if (last[m]) ok = ok && single_claim_ok(x[m] ^ ra[m] ^ rb[m], ra[m], rb[m]);
+        nlast += last[m] ? 1u : 0u;
+      }
+      uint32_t lab[4], ncl[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        lab[m] = x[m];
+        ncl[m] = x[m] != 0u;
+      }
+      bool exact_ok = true;
+      if (!__all(single && ok)) {
+        if (lds_counts) {
+          // exact claim sets, as for short rows: parity of every distinct
+          // region after crossing i = parity of the crossings <= i toggling
+          // it (lanes before: one ballot; this lane: a running xor)
+          const uint64_t before = (1ull << lane) - 1ull;
+          if (lane < kLutLds / 32) rbits[w][lane] = 0u;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            lab[m] = 0u;
+            ncl[m] = 0u;
+            if (live[m]) {
+              if (ra[m]) atomicOr(&rbits[w][ra[m] >> 5], 1u << (ra[m] & 31u));
+              if (rb[m]) atomicOr(&rbits[w][rb[m] >> 5], 1u << (rb[m] & 31u));
+            }
+          }
+          const int nwords = (R + 32) >> 5;
+          for (int wi = 0; wi < nwords; ++wi) {
+            uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)rbits[w][wi]);
+            while (bits) {
+              const uint32_t v = (uint32_t)wi * 32u + (uint32_t)__builtin_ctz(bits);
+              bits &= bits - 1u;
+              uint32_t t[4], par = 0u;
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                t[m] = (live[m] && ((ra[m] == v) != (rb[m] == v))) ? 1u : 0u;
+                par ^= t[m];
+              }
+              uint32_t run = (uint32_t)__popcll(__ballot(par != 0u) & before) & 1u;
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                run ^= t[m];
+                if (live[m] && run) {
+                  ++ncl[m];
+                  lab[m] = max(lab[m], v);
+                }
+              }
+            }
+          }
+        } else {
+          exact_ok = false;   // more regions than the bitmap holds: serial walk
+        }
+      }
+      if (__all(exact_ok)) {
+        const uint32_t incl = wave_add_scan(nlast);
+        uint32_t idx = incl - nlast;       // groups before this lane's first crossing
+        unsigned long long cont = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if (!last[m]) continue;
+          sp_start[w][1 + idx] = (uint16_t)p[m];
+          sp_lab[w][1 + idx] = (uint16_t)lab[m];
+          ++idx;
+          const uint32_t i = 4 * (uint32_t)lane + m;
+          const uint32_t en = i + 1 == cnt ? (uint32_t)N : pn[m];
+          if (en > p[m]) {
+            if (lds_counts) atomicAdd(&lcount[lab[m]], en - p[m]);
+            else g_atomic_add((g_ptr<unsigned long long>)&I.counts[lab[m]], (unsigned long long)(en - p[m]));
+            if (ncl[m] > 1) cont += en - p[m];
+          }
+        }
+        if (lane == 0) {
+          sp_start[w][0] = 0;
+          sp_lab[w][0] = 0;
+          if (p[0] > 0) {
+            if (lds_counts) atomicAdd(&lcount[0], p[0]);
+            else g_atomic_add((g_ptr<unsigned long long>)&I.counts[0], (unsigned long long)p[0]);
+          }
+        }
+        if (__any(cont != 0ull)) {
+          for (int d = 32; d >= 1; d >>= 1) cont += __shfl_xor(cont, d, 64);
+          if (lane == 0) {
+            atomicAdd(&contested_blk, cont);
+            g_atomic_or(&I.st->flags, (int32_t)CG_FLAG_CONTESTED);
+          }
+        }
+        ngroups = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      } else {
+        serial = true;
+      }
+    }
+    if (serial && lane == 0) {
+      // exact serial walk of the claim set
       Claims cl;
       cl.cur = 0;
       cl.multi = false;

@@ -100,3 +100,22 @@ def test_bad_series_arguments_are_rejected_before_launch(ctx):
         d.update(kw)
         with pytest.raises(B.CartogramError):
             ctx.step_series([d])
+
+
+def test_map_destroyed_after_its_context():
+    """A map freed after its context leaves no device error behind: the next
+    context's launches run (regression: the map read its device through the
+    freed context)."""
+    from paper_2604_13880_amd import binding as B
+    m = square_grid_map(2, 2)
+    c1 = B.Context(0)
+    gm = c1.map_from(m)
+    c1.close()
+    del gm
+    import gc
+    gc.collect()
+    c2 = B.Context(0)
+    g2 = c2.map_from(m)
+    r = c2.step_series([dict(map=g2, xy0=m.xy32(), N=64, values=np.ones(4, np.float32), fixed_iters=1)])[0]
+    assert r["iters"][0] == 1
+    c2.close()
