@@ -218,6 +218,23 @@ __device__ __forceinline__ double dpp_take(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
+// Lane l takes lane l+1's value (lane 63 takes 0) / lane l-1's (lane 0 takes 0).
+template <typename Lc>
+__device__ __forceinline__ Lc take_right(Lc v) { return dpp_take<0x130, 0xf>(v); }   // wave_shl:1
+template <typename Lc>
+__device__ __forceinline__ Lc take_left(Lc v) { return dpp_take<0x138, 0xf>(v); }    // wave_shr:1
+// One lane's value (uniform lane index) and a write into one lane.
+__device__ __forceinline__ float lane_get(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_get(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename Lc>
+__device__ __forceinline__ Lc lane_put(Lc x, int l, Lc old) { return (int)(threadIdx.x & 63) == l ? x : old; }
+
 template <typename Lc>
 __device__ __forceinline__ Lc wave_inclusive_scan_dpp(Lc x) {
   x += dpp_take<0x111, 0xf>(x);   // row_shr:1
@@ -430,7 +447,17 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   else if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
   typedef typename LocalT<P>::type Lc;
-  Lc col = 0, ha0 = 0, ha1 = 0, hb0 = 0, hb1 = 0;
+  // Line sums by shift registers over each wavefront's 64-column strip:
+  // after row r, lane c of `sa` holds the strip's mass on the anti-diagonal
+  // through (c, r) above that row (it moves one lane left per row) and lane
+  // c of `sd` the mass on the diagonal (one lane right per row).  The sum
+  // leaving the strip at its left (anti-diagonal) or right (diagonal) edge
+  // after row r is complete; it is kept in lane r of oa / od.  The strips'
+  // partial line sums are added per tile afterwards.
+  constexpr int HP = 64 + TH - 1;           // line sums touching one strip
+  __shared__ Lc hpa[NW][HP];
+  __shared__ Lc hpb[NW][HP];
+  Lc col = 0, sa = 0, sd = 0, oa = 0, od = 0;
   const int c1 = t + TW;
   const bool has1 = c1 < D;
   Stager<DENSE, SB, TW, TW> stg;
@@ -448,30 +475,40 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
       v = wave_inclusive_scan_dpp(v);       // lane 63 holds the row total
       if (lane == 63) acc_zero(rsum[r0 + rr]), acc_add_local(rsum[r0 + rr], v);
     }
-    // branch-free: clamped indices and selects
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr;
-      col += (Lc)ds[rr][t];
-      const int ca = t - r;                 // anti-diagonal slot t meets row r here
-      const Lc va = (Lc)ds[rr][ca < 0 ? 0 : ca];
-      ha0 += ca >= 0 ? va : (Lc)0;
-      const int cb = t + r - TH + 1;        // diagonal slot t
-      const Lc vb = (Lc)ds[rr][cb < 0 ? 0 : cb];
-      hb0 += cb >= 0 ? vb : (Lc)0;
-    }
-    if (has1) {                             // slots t + TW (always right of column 0)
-#pragma unroll
-      for (int rr = 0; rr < SB; ++rr) {
-        const int r = r0 + rr;
-        const int ca1 = c1 - r, cb1 = c1 + r - TH + 1;
-        const Lc va = (Lc)ds[rr][ca1 < TW ? ca1 : TW - 1];
-        const Lc vb = (Lc)ds[rr][cb1 < TW ? cb1 : TW - 1];
-        ha1 += ca1 < TW ? va : (Lc)0;
-        hb1 += cb1 < TW ? vb : (Lc)0;
+      const Lc d = (Lc)ds[rr][t];
+      col += d;
+      if (r > 0) {
+        oa = lane_put(lane_get(sa, 0), r - 1, oa);    // anti-diagonal s = r - 1 of the strip
+        od = lane_put(lane_get(sd, 63), r - 1, od);   // diagonal s = TH + 63 - r of the strip
       }
+      sa = d + take_right(sa);
+      sd = d + take_left(sd);
     }
   }
+  // strip partials: anti-diagonal s (c + r, strip columns) at hpa[s],
+  // diagonal s (c - r + TH - 1) at hpb[s]; then the tile's line sums,
+  // strips in order
+  hpa[w][lane + TH - 1] = sa;
+  hpb[w][lane] = sd;
+  if (lane < TH - 1) {
+    hpa[w][lane] = oa;
+    hpb[w][TH + 62 - lane] = od;
+  }
+  __syncthreads();
+  auto line = [&](const Lc (*hp)[HP], int s) -> Lc {
+    Lc v = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      const int o = s - 64 * ww;
+      if (o >= 0 && o < HP) v += hp[ww][o];
+    }
+    return v;
+  };
+  const Lc ha0 = line(hpa, t), hb0 = line(hpb, t);
+  const Lc ha1 = has1 ? line(hpa, c1) : (Lc)0, hb1 = has1 ? line(hpb, c1) : (Lc)0;
   __syncthreads();
   g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   const int64_t tid = (int64_t)ty * L.ntx + tx;
