@@ -849,16 +849,25 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef RowStage<DENSE, XW, NW> Stage;
   Stage stg;
   stg.init(I);
+  // pipeline: the labels of the sub-band after next and the densities
+  // (table lookups) of the next one are in flight while a sub-band is done
+  float dnext[8];
   stg.load(I, x0 - TH, y0);
+  stg.values(I, dnext);
+  if (SB < TH) stg.load(I, x0 - TH, y0 + SB);
   for (int r0 = 0; r0 < TH; r0 += SB) {
     // T of the previous sub-band; then this sub-band's densities and
     // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, each
     // row scanned by one segment of a wavefront (8 columns per lane)
+    float dv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dv[e] = dnext[e];
+    if (r0 + SB < TH) {
+      stg.values(I, dnext);
+      if (r0 + 2 * SB < TH) stg.load(I, x0 - TH, y0 + r0 + 2 * SB);
+    }
     if (r0 > 0) t_pass(r0 - SB);
     {
-      float dv[8];
-      stg.values(I, dv);
-      if (r0 + SB < TH) stg.load(I, x0 - TH, y0 + r0 + SB);   // next sub-band in flight
       Lc loc = 0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) loc += (Lc)dv[e];
