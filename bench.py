@@ -541,6 +541,60 @@ def run_uneven(a, B, ctx, torch):
                 single_calls_ms_per_cartogram=ms_single, single_calls_maps=k, ms_to_1pct=to_tol, roofline=roof)
 
 
+BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of the MI355X
+
+
+def net_flops(cfg, batch):
+    """Multiply-adds x 2 of one forward pass: every 3x3 convolution (encoder
+    and decoder levels) and the 1x1 head, per the net's layer table."""
+    c, L, H, W, cin = cfg["base_channels"], cfg["levels"], cfg["height"], cfg["width"], cfg.get("in_channels", 1)
+    f = 0
+    for l in range(L):
+        px = (H >> l) * (W >> l)
+        ci = cin if l == 0 else c << (l - 1)
+        f += 2 * 9 * px * (ci * (c << l) + (c << l) * (c << l))
+    for l in range(L - 2, -1, -1):
+        px = (H >> l) * (W >> l)
+        f += 2 * 9 * px * (((c << (l + 1)) + (c << l)) * (c << l) + (c << l) * (c << l))
+    f += 2 * H * W * c * 2
+    return f * batch
+
+
+def net_throughput(B, ctx, cfg, torch, batch=32, reps=10):
+    """Forward passes and training steps (forward, backward, Adam) of the
+    shipped net at batch 32, timed by events on the current stream: TFLOP/s
+    of the convolutions against the bf16 matrix-core peak (a training step
+    counts 3x the forward's flops: forward, input and weight gradients)."""
+    net = B.Net(ctx, max_batch=batch, **cfg)
+    x = torch.randn((batch, cfg["height"], cfg["width"], cfg["in_channels"]), device="cuda")
+    tgt = 0.05 * torch.randn((batch, cfg["height"], cfg["width"], 2), device="cuda")
+    for _ in range(2):
+        net.forward(x)
+        net.zero_grads()
+        net.backward(tgt)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(reps):
+        net.forward(x)
+    e1.record()
+    for _ in range(reps):
+        net.forward(x)
+        net.backward(tgt)
+        net.adam_step(1e-4)
+    e2.record()
+    torch.cuda.synchronize()
+    f = net_flops(cfg, batch)
+    fwd_ms = e0.elapsed_time(e1) / reps
+    step_ms = e1.elapsed_time(e2) / reps
+    net.close()
+    fwd_tf = f / (fwd_ms * 1e-3) / 1e12
+    step_tf = 3 * f / (step_ms * 1e-3) / 1e12
+    return dict(batch=batch, gflop_forward=f / 1e9, forward_ms=fwd_ms, train_step_ms=step_ms,
+                forward_tflops=fwd_tf, train_step_tflops=step_tf, peak_tflops=BF16_PEAK_TFLOPS,
+                mfma_frac_forward=fwd_tf / BF16_PEAK_TFLOPS, mfma_frac_train=step_tf / BF16_PEAK_TFLOPS)
+
+
 def run_learned(a, B, ctx, torch):
     """Warm start by the trained net followed by the plain
     iteration, against the plain method, on held-out seeded maps."""
@@ -562,6 +616,7 @@ def run_learned(a, B, ctx, torch):
     rep["configured_form_note"] = ("the configured net input is the 512^2 density texture; the net here sees the "
                                    f"log-density and a one-iteration tracer field on a {Lr.N_NET}^2 grid (measured "
                                    "better and cheaper than a 512^2 net); the 512^2 form is not run")
+    rep["net"] = net_throughput(B, ctx, Lr.NET_CFG, torch)
     rep["speedup_learned_batched_vs_plain_single"] = rep["plain_single_ms_per_cartogram"] / rep["warm_ms_per_cartogram"]
     rep["speedup_learned_batched_vs_plain_batched"] = rep["plain_ms_per_cartogram"] / rep["warm_ms_per_cartogram"]
     eq = rep["equal_quality"]
@@ -603,6 +658,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start at 512^2")
     ap.add_argument("--no-forms", action="store_true", help="skip the background-mass series and the sweeps")
     ap.add_argument("--learned-maps", type=int, default=64, help="held-out maps of the learned comparison")
+    ap.add_argument("--parts", default="main,series,uneven,learned,forms,cpu",
+                    help="comma list of main (the timed 1024^2 workload), series, uneven, learned, forms, cpu; "
+                         "profiling runs select one (the JSON line then holds null for the rest)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
     a = ap.parse_args()
@@ -624,8 +682,11 @@ def main():
     from paper_2604_13880_amd import binding as B
     from synth import lognormal_values, voronoi_map
 
+    parts = set(a.parts.split(","))
+    if "main" not in parts:
+        a.steps = 0
     w = WORKLOADS[a.workload]
-    nseed = w.get("seeds", 1)
+    nseed = w.get("seeds", 1) if "main" in parts else 1
     log("workload", a.workload, "generating", nseed, "maps")
     maps = [(voronoi_map(w["seed"] + k, w["R"], w["n"], fractal=w["fractal"]),
              lognormal_values(w["seed"] + k, w["R"], w["sigma"]).astype(np.float32)) for k in range(nseed)]
@@ -642,12 +703,14 @@ def main():
     # untimed: one run of every map (workspaces, code), the requested
     # warm-up runs, then every stage timed once on the first map
     log("preparing", nseed, "maps, warmup", a.warmup)
-    for k in range(nseed):
-        ctx.step_series([descs[k]], graph_iters=a.graph_iters)
-    for k in range(a.warmup):
-        ctx.step_series([descs[k % nseed]], graph_iters=a.graph_iters)
+    if "main" in parts:
+        for k in range(nseed):
+            ctx.step_series([descs[k]], graph_iters=a.graph_iters)
+        for k in range(a.warmup):
+            ctx.step_series([descs[k % nseed]], graph_iters=a.graph_iters)
     torch.cuda.synchronize()
-    tab = stage_table(ctx, [descs[0]], [inst_info(m, gmaps[0], N)], w["precision"], -32) if a.stage_tables else {}
+    tab = stage_table(ctx, [descs[0]], [inst_info(m, gmaps[0], N)], w["precision"], -32) \
+        if (a.stage_tables and "main" in parts) else {}
     stage = a.stage
     if stage is None:
         stage = max(tab, key=lambda s: tab[s]["avg_us"] * tab[s]["launches"]) if tab else "sat_final"
@@ -663,39 +726,41 @@ def main():
     t1 = time.perf_counter()
     stage_ms, stage_n = ctx.profile_read()
     ctx.profile_stage(None)
-    ms_step = (t1 - t0) * 1e3 / a.steps
-    its = np.array([int(r["iters"][0]) for r in runs])
-    xis = np.array([float(r["xi"][0]) for r in runs])
-    sts = np.array([int(r["status"][0]) for r in runs])
+    ms_step = (t1 - t0) * 1e3 / max(a.steps, 1)
+    its = np.array([int(r["iters"][0]) for r in runs] or [0])
+    xis = np.array([float(r["xi"][0]) for r in runs] or [0.0])
+    sts = np.array([int(r["status"][0]) for r in runs] or [2])
     iters = float(its.mean())
-    mpx = N * N * float(its.sum()) / ((t1 - t0)) / 1e6
+    mpx = N * N * float(its.sum()) / max(t1 - t0, 1e-9) / 1e6
     # bytes per launch of the timed stage over the maps of the timed steps
     info = [inst_info(maps[k % nseed][0], gmaps[k % nseed], N) for k in range(a.steps)]
     by = [alg_bytes(stage, i["N"], w["precision"], i["n_pts"], i["n_edges"], i["ring_len"]) for i in info]
     per = None if any(b is None for b in by) else float(np.mean(by))
     roof = roofline(stage, stage_ms, stage_n, per, a.workload)
     reached = int((sts == 0).sum())
-    q_c2 = quality_of(ctx, [(gmaps[k], descs[k]["xy0"], runs[k]["xy"][0]) for k in range(min(nseed, a.steps))], N)
+    q_c2 = quality_of(ctx, [(gmaps[k], descs[k]["xy0"], runs[k]["xy"][0]) for k in range(min(nseed, a.steps))], N) \
+        if runs else None
 
+    full = a.workload == "fractal100_1024"
     series = None
-    if not a.no_series and a.workload == "fractal100_1024":
+    if not a.no_series and full and "series" in parts:
         series = run_series(a, WORKLOADS["series64_fractal200_2048"], B, ctx, torch)
 
     uneven = None
-    if not a.no_uneven and a.workload == "fractal100_1024":
+    if not a.no_uneven and full and "uneven" in parts:
         uneven = run_uneven(a, B, ctx, torch)
 
     learned = None
-    if not a.no_learned and a.workload == "fractal100_1024":
+    if not a.no_learned and full and "learned" in parts:
         learned = run_learned(a, B, ctx, torch)
 
     bgmass = sweeps = None
-    if not a.no_forms and a.workload == "fractal100_1024":
+    if not a.no_forms and full and "forms" in parts:
         bgmass = run_background_mass(a, ctx, B, torch)
         sweeps = run_sweeps(a, ctx, B, torch)
 
     cpu = None
-    if not a.no_cpu:
+    if not a.no_cpu and "cpu" in parts:
         log("cpu baseline", a.cpu_iters, "iterations")
         cpu = cpu_baseline(w, iters, a.cpu_iters, a.cpu_workers)
 

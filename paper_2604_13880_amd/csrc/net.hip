@@ -260,14 +260,21 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
     }
 }
 
-// dst[i] += sum over z = 0..parts-1 of part[z][i], in that order.
+// dst[i] += sum over z = 0..parts-1 of part[z][i] in a fixed order: a
+// block takes 64 consecutive elements (one per lane, so every load is 256
+// contiguous bytes); wavefront g sums the shares z = g, g+4, g+8, ... in
+// increasing z, and the four partial sums are added in g order.
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int64_t n, int parts,
                                                    float* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int z = 0; z < parts; ++z) s += part[(int64_t)z * n + i];
-  dst[i] += s;
+  if (i < n)
+    for (int z = g; z < parts; z += 4) s += part[(int64_t)z * n + i];
+  red[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && i < n) dst[i] += ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // dst[0] += sum over z of part[z] (FP64), fixed order: strided sums per
@@ -610,7 +617,9 @@ void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* ou
 int64_t wgrad_splits(int64_t P, int Cin, int Cout, int64_t* px_per_block) {
   const int K = 9 * Cin;
   const int64_t kt = (K + 127) / 128, ot = Cout / 32;
+  // (at most 256 shares: their fixed-order sum stays short)
   int64_t splits = 4096 / (kt * ot);
+  if (splits > 256) splits = 256;
   if (splits < 1) splits = 1;
   int64_t ppb = (P + splits - 1) / splits;
   if (ppb < 256) ppb = 256;
@@ -633,7 +642,7 @@ void launch_conv3_wgrad(const uint16_t* in, int Cin, const uint16_t* g, int Cout
   else
     hipLaunchKernelGGL((k_conv3_wgrad<true>), grid, dim3(256), 0, s, in, Cin, g, Cout, part, P, H, W, ppb);
   const int64_t n = (int64_t)Cout * K;
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(n)), dim3(256), 0, s, part, n, (int)splits, dW);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part, n, (int)splits, dW);
 }
 
 void launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s) {
@@ -659,9 +668,9 @@ void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, f
   hipLaunchKernelGGL(k_skip_grad, dim3(nblk((int64_t)Bn * H * W * (Cs / 8))), dim3(256), 0, s, gcat, Ccat, Cd, gpool,
                      gskip, Cs, Bn, H, W);
 }
-// Blocks of the bias gradient (at most 1024, at least 64 pixels each).
+// Blocks of the bias gradient (at most 256, at least 64 pixels each).
 int64_t bias_blocks(int64_t P, int64_t* px_per_block) {
-  int64_t blocks = 1024;
+  int64_t blocks = 256;
   int64_t ppb = (P + blocks - 1) / blocks;
   if (ppb < 64) ppb = 64;
   if (px_per_block) *px_per_block = ppb;
@@ -674,7 +683,7 @@ void launch_bias_grad(const float* g, const uint16_t* act, int C, int64_t P, flo
   int64_t ppb = 0;
   const int64_t blocks = bias_blocks(P, &ppb);
   hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)blocks), dim3(256), 0, s, g, act, C, P, ppb, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(C)), dim3(256), 0, s, part, (int64_t)C, (int)blocks, db);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s, part, (int64_t)C, (int)blocks, db);
 }
 void launch_head_fwd(const uint16_t* x, int C, const float* w, const float* b, float scale, const float* resid,
                      int rc, float gain, float* out, int64_t P, hipStream_t s) {
@@ -686,7 +695,8 @@ void launch_head_bwd(const uint16_t* x, int C, const float* w, float scale, cons
                      int64_t P, float* gx, float* dw, double* loss, float* part, double* lpart, hipStream_t s) {
   const unsigned blocks = nblk(P);
   hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, x, C, w, scale, out, target, P, gx, part, lpart);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(2 * C + 2)), dim3(256), 0, s, part, (int64_t)(2 * C + 2), (int)blocks, dw);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((2 * C + 2 + 63) / 64)), dim3(256), 0, s, part, (int64_t)(2 * C + 2),
+                     (int)blocks, dw);
   if (loss) hipLaunchKernelGGL(k_sum_parts_f64, dim3(1), dim3(256), 0, s, lpart, (int)blocks, loss);
 }
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
