@@ -462,14 +462,16 @@ def iterate_once(xy, m, values, N, b=1.0, area_source="pixel", extra=None, bg_ma
 
 
 def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
-        area_source="pixel", fixed_iters=None, state_dtype=np.float64, extra=None, bg_mass=None) -> RunResult:
+        area_source="pixel", fixed_iters=None, state_dtype=np.float64, extra=None, bg_mass=None,
+        progress=None) -> RunResult:
     """Iterate until xi < tol, no new minimum in `patience` iterations, or
     max_iters (or exactly `fixed_iters` iterations when given).
 
     `state_dtype` is the precision the positions are kept in between
     iterations (float64 by default; float32 reproduces a float32 state,
     whose snapping to the raster grid is then decided in the same
-    precision as a float32 implementation)."""
+    precision as a float32 implementation).  `progress(k, xi)`, when
+    given, is called after every iteration (reporting only)."""
     xy = np.asarray(m.xy if xy0 is None else xy0, np.float64).astype(state_dtype).astype(np.float64)
     if extra is not None:
         extra = np.asarray(extra, np.float64).astype(state_dtype).astype(np.float64)
@@ -501,6 +503,8 @@ def run(m, values, N, xy0=None, b=1.0, tol=0.01, patience=32, max_iters=512,
         A = region_areas(xy, m.ring_off, m.ring_idx, m.ring_reg, m.n_regions)
         eps, xi = cartographic_errors(A, values)
         hist.append(xi)
+        if progress is not None:
+            progress(k, xi)
         if xi < best:
             best, best_k = xi, k
     return RunResult(xy=xy, iters=k, status=status, eps=eps, xi=xi, xi_history=hist, extra=extra)

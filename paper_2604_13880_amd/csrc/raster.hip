@@ -17,8 +17,9 @@
 //                   appended to the bucket of every row the edge crosses
 //                   (kFillXing records per row; an integer atomic per
 //                   crossing picks the slot)
-//   k_raster_fill   one wavefront per row: sort by p0, walk, write labels,
-//                   per-region counts aggregated in LDS
+//   k_raster_fill   one wavefront per row: rank sort by p0, claim sets by
+//                   lane scans, write labels, per-region counts aggregated
+//                   in LDS
 #include "cg_dev.h"
 
 namespace cgk {
@@ -222,13 +223,18 @@ __device__ __forceinline__ uint32_t wave_add_scan(uint32_t x) {
   return x;
 }
 
-// One wavefront per row.  Crossings sorted by p0; t = A xor B for every
+// One wavefront per row (up to 64 crossings one per lane, up to 256 four
+// per lane).  Crossings rank-sorted by (p0, slot); t = A xor B for every
 // crossing; the inclusive xor-scan X gives the claiming region after every
 // prefix as long as at most one region claims (the claim set starts empty
 // at the left border).  A crossing alone at its p0 keeps the set a
-// singleton iff the label before it is one of its two regions; rows that
-// fail this test, or have several crossings at one p0, take the exact
-// serial walk instead (folded maps, coincident crossings).
+// singleton iff the label before it is one of its two regions.  Rows that
+// fail this test, or have several crossings at one p0 (a boundary wiggling
+// inside one pixel, or a folded map), take exact claim sets: for every
+// distinct region of the row (a bitmap in LDS), its membership after
+// crossing k is the parity of the crossings <= k with that region on one
+// side only (a ballot and a popcount).  The serial walk of the claim set
+// remains for long rows of maps with more regions than the bitmap holds.
 __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_rows, KD_ROWS, blockIdx.x, first);

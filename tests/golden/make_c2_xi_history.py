@@ -6,7 +6,8 @@ minimum within 32 iterations, at most 512 iterations; pixel-count
 density, shape parameter 1).
 
 Calls only the oracle and the seeded input generators.  Takes about
-three minutes per map and core; the maps run in parallel processes.
+one to three minutes per map and core, depending on the host; the maps
+run in parallel processes and report every 64 iterations.
 
     python tests/golden/make_c2_xi_history.py [--workers 8]
 """
@@ -37,7 +38,12 @@ def one(seed: int):
     m = voronoi_map(seed, R, N_VERT, fractal=True)
     s = lognormal_values(seed, R, SIGMA).astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
-    r = oc.run(m, s, N)
+
+    def report(k, xi):
+        if k % 64 == 0:
+            print(f"seed {seed}: iteration {k}, xi {xi:.4f} ({time.perf_counter() - t0:.0f} s)", flush=True)
+
+    r = oc.run(m, s, N, progress=report)
     return seed, r.iters, r.status, r.eps, r.xi, r.xi_history, time.perf_counter() - t0
 
 
@@ -47,9 +53,13 @@ def main():
     ap.add_argument("--out", default=os.path.join(HERE, "c2_xi_history.txt"))
     a = ap.parse_args()
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(a.workers) as pool:
-        res = sorted(pool.map(one, SEEDS, chunksize=1))
     names = ["converged", "stalled", "maxiter"]
+    res = []
+    with mp.get_context("fork").Pool(a.workers) as pool:
+        for r in pool.imap_unordered(one, SEEDS, chunksize=1):   # each map reported as it ends
+            res.append(r)
+            print(f"seed {r[0]}: {r[1]} iterations, {names[r[2]]}, xi {r[4]:.4f} ({r[6]:.0f} s)", flush=True)
+    res.sort()
     with open(a.out, "w") as fh:
         fh.write("# Max area error history of the FP64 oracle on the ten seeded 1024^2\n"
                  "# cartograms (100 fractal Voronoi regions, ~50k vertices, lognormal\n"
@@ -65,7 +75,6 @@ def main():
             for k, v in enumerate(hist):
                 if k % EVERY == 0 or k == len(hist) - 1:
                     fh.write(f"xi {seed} {k} {v:.9g}\n")
-            print(f"seed {seed}: {iters} iterations, {names[status]}, xi {xi:.4f} ({dt:.0f} s)", flush=True)
 
 
 if __name__ == "__main__":
