@@ -31,6 +31,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import platform
@@ -105,11 +106,20 @@ def alg_bytes(stage, N, prec, n_pts, n_edges=0, ring_len=0):
     return None
 
 
+def code_text(text):
+    """Source text without comments, trailing blanks and empty lines: the
+    part of a kernel source that changes what is compiled."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def sources_hash(stage):
+    """Hash of the code (comments left out) of the sources a kernel is built from."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES.get(stage, []):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
