@@ -22,7 +22,7 @@ region), measured with HIP events recorded on the kernel's own stream
 around one launch in every `--profile-every` iterations of the timed
 region; the rocprofv3 duration of the same kernel and workload from the
 summary under profiles/ is reported beside it when that summary was taken
-on the current kernel source, and so is `traffic` (HBM bytes per launch
+on the current kernel code, and so is `traffic` (HBM bytes per launch
 from the FETCH_SIZE / WRITE_SIZE counters).  `cpu_baseline` times the FP64
 oracle on a bounded sample of the same workload on the host cores, one
 process per core.
