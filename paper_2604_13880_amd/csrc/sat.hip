@@ -117,46 +117,6 @@ constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of th
 constexpr int kPrefLds = 1024;    // tile-row prefix totals the carry pass keeps in LDS
 constexpr int kReduce_Rows = 8;   // rows per sub-band of the reduce pass (every thread loads)
 
-// Row prefix sums of one sub-band: M[rr][c] = base + (L(c) - L(c0)) + d(c)/2
-// where L is the exclusive prefix of the row over the staged columns and
-// c0 the column where the carried base applies (0 for a tile without halo).
-template <typename A, int W, int NW>
-__device__ __forceinline__ void sub_band_scan(const float (*ds)[W], A (*Ms)[W], const A* base, int c0,
-                                              A* rowtot) {
-  constexpr int E = W / 64 + 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int rr = w; rr < kSub_Rows; rr += NW) {
-    float dv[E];
-    A loc;
-    acc_zero(loc);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int c = lane * E + e;
-      dv[e] = c < W ? ds[rr][c] : 0.f;
-      acc_add(loc, dv[e]);
-    }
-    A run = wave_exclusive_scan(loc, lane);
-    A lv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      lv[e] = run;
-      acc_add(run, dv[e]);
-    }
-    const A l0 = shfl_acc(lv[c0 % E], c0 / E);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int c = lane * E + e;
-      if (c < W) {
-        A v = base[rr];
-        acc_addv(v, acc_sub(lv[e], l0));
-        acc_add(v, 0.5f * dv[e]);
-        Ms[rr][c] = v;
-      }
-    }
-    if (rowtot && lane == 63) rowtot[rr] = run;   // local row total (c0 = 0, base 0)
-  }
-}
-
 __device__ __forceinline__ float shfl_xor_acc(float v, int d) { return __shfl_xor(v, d, 64); }
 __device__ __forceinline__ double shfl_xor_acc(double v, int d) { return __shfl_xor(v, d, 64); }
 __device__ __forceinline__ Comp shfl_xor_acc(Comp v, int d) {
@@ -275,72 +235,60 @@ __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t rs, int voff,
   else if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, voff, soff, kNT);
   else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, soff, kNT);
 }
-// Eight consecutive LDS values (16-byte aligned) in 16-byte stores.
-__device__ __forceinline__ void store8(float* p, const float v[8]) {
-  *(f32x4_t*)p = f32x4_t{v[0], v[1], v[2], v[3]};
-  *(f32x4_t*)(p + 4) = f32x4_t{v[4], v[5], v[6], v[7]};
-}
-__device__ __forceinline__ void store8(double* p, const double v[8]) {
-#pragma unroll
-  for (int e = 0; e < 8; e += 2) *(f64x2_t*)(p + e) = f64x2_t{v[e], v[e + 1]};
+// Four consecutive LDS values (16-byte aligned) in 16-byte stores.
+__device__ __forceinline__ void store4(float* p, const float v[4]) { *(f32x4_t*)p = f32x4_t{v[0], v[1], v[2], v[3]}; }
+__device__ __forceinline__ void store4(double* p, const double v[4]) {
+  *(f64x2_t*)p = f64x2_t{v[0], v[1]};
+  *(f64x2_t*)(p + 2) = f64x2_t{v[2], v[3]};
 }
 
-// One sub-band of kSub_Rows rows of a W-column strip, one row per segment
-// of SEG lanes, 8 consecutive columns per lane: wavefront w holds rows
-// w*RPP .. w*RPP+RPP-1.  The labels (or densities) of the next sub-band
-// are loaded while the current one is scanned.
+// One sub-band of kSub_Rows rows of a tile's W columns, one row per segment
+// of W/4 lanes (16, 32 or 64), 4 consecutive columns per lane: wavefront w
+// holds rows w*RPP .. w*RPP+RPP-1.  The labels (or densities) of a later
+// sub-band are loaded while the current one is scanned.
 template <bool DENSE, int W, int NW>
 struct RowStage {
-  static constexpr int LPR = W / 8;                    // lanes per row
-  static constexpr int SEG = (LPR + 15) / 16 * 16;
-  static constexpr int RPP = 64 / SEG;                 // rows per wavefront
-  static_assert(W % 8 == 0 && SEG <= 64 && NW * RPP == kSub_Rows, "one pass covers the sub-band");
+  static constexpr int LPR = W / 4;                    // lanes per row = segment
+  static constexpr int RPP = 64 / LPR;                 // rows per wavefront
+  static_assert(LPR == 16 || LPR == 32 || LPR == 64, "segments are whole DPP rows");
+  static_assert(NW * RPP == kSub_Rows, "one pass covers the sub-band");
   // Labels and LUT entries are read with buffer loads: an offset past the
   // descriptor's byte count reads 0, so chunks outside the texture and
   // labels outside the LUT need no branch (kOut marks them).
   static constexpr uint32_t kOut = 0x80000000u;
   __amdgpu_buffer_rsrc_t lab_rs, lut_rs;
-  u32x4_t lab;
-  f32x4_t da, db;
+  u32x2_t lab;
+  f32x4_t da;
   bool ok;
-  bool act;    // the lane holds a chunk of a row of the sub-band
   int g, li;   // row of the sub-band, chunk of the row
 
   __device__ __forceinline__ void init(const InstG& I) {
     const int lane = threadIdx.x & 63;
-    g = (threadIdx.x >> 6) * RPP + lane / SEG;
-    li = lane % SEG;
-    act = lane / SEG < RPP && li < LPR;   // g < kSub_Rows
+    g = (threadIdx.x >> 6) * RPP + lane / LPR;
+    li = lane % LPR;
     if (!DENSE) {
       lab_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.labels, (short)0, (int)(2 * (int64_t)I.N * I.N), 0x00020000);
       lut_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.lut, (short)0, 4 * I.n_lut, 0x00020000);
     }
   }
   __device__ __forceinline__ void load(const InstG& I, int xs, int y) {
-    const int N = I.N, q = y + g, p = xs + 8 * li;
-    ok = act && q < N && p >= 0 && p < N;   // p, N multiples of 8: whole chunks
+    const int N = I.N, q = y + g, p = xs + 4 * li;
+    ok = q < N && p < N;   // p >= 0; p and N multiples of 4: whole chunks
     if (DENSE) {
-      if (ok) {
-        const int64_t at = (int64_t)q * N + p;
-        da = *(g_ptr<const f32x4_t>)(I.density + at);
-        db = *(g_ptr<const f32x4_t>)(I.density + at + 4);
-      }
+      if (ok) da = *(g_ptr<const f32x4_t>)(I.density + (int64_t)q * N + p);
     } else {
       const uint32_t off = ok ? (uint32_t)(2 * ((int64_t)q * N + p)) : kOut;   // N^2 * 2 < 2^31
-      lab = __builtin_amdgcn_raw_buffer_load_b128(lab_rs, (int)off, 0, 0);
+      lab = __builtin_amdgcn_raw_buffer_load_b64(lab_rs, (int)off, 0, 0);
     }
   }
-  __device__ __forceinline__ void values(const InstG& I, float v[8]) const {
+  __device__ __forceinline__ void values(const InstG& I, float v[4]) const {
     if (DENSE) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        v[e] = ok ? da[e] : 0.f;
-        v[4 + e] = ok ? db[e] : 0.f;
-      }
+      for (int e = 0; e < 4; ++e) v[e] = ok ? da[e] : 0.f;
     } else {
       const uint32_t out = ok ? 0u : kOut;   // zero mass outside the texture
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < 4; ++e) {
         const uint32_t lb = (lab[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
         v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(lut_rs, (int)((lb << 2) | out), 0, 0));
       }
@@ -706,16 +654,28 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   }
 }
 
-// Writer pass.  Per tile (TW threads, one per node column, TH rows, halo
-// of TH columns on both sides for the tilted areas):
+// Writer pass.  Per tile (TW threads, one per node column, TH rows; the
+// tile's own labels only):
 //   S(i, j) = Stop(i) + sum_{rows < j} rc(q) + sum_{rows < j} Rloc(i, q)
 //   TA(s, j) = TAc(s) + sum_{rows < j} rc(q) + la(s, j)   (likewise TB)
 //   T = TA - TB = (TAc - TBc) + (la - lb)   (the row-carry sums cancel)
-// where rc(q) is the row integral left of the tile, Rloc/Mloc the row
-// integral from the tile's left edge (to the node / to the pixel centre)
-// and la, lb the running sums of Mloc along each anti-diagonal / diagonal
-// slot.  Rloc, Mloc, la, lb stay within one tile and are kept in the
-// local type; Stop, TAc, TBc and the row-carry sum in the accumulator.
+// where rc(q) is the row integral left of the tile, Rloc the row integral
+// from the tile's left edge to the node and la, lb the sums of Mloc (the
+// row integral from the tile's left edge to a pixel centre) along the
+// anti-diagonal / diagonal through the node over the tile's rows above it.
+// Those lines may start in a neighbouring tile of the same tile row; their
+// part there is known from the reduce pass: an anti-diagonal that lies in
+// the right tile up to row k adds the tile's own row totals of rows 0..k
+// plus the right tile's mass below its anti-diagonal k; a diagonal that
+// lies in the left tile adds that tile's mass below the diagonal minus
+// its total (Mloc is negative left of the tile).  Inside the tile the
+// line sums run in shift registers: after every row the anti-diagonal sums
+// move one lane left, the diagonal sums one lane right, and every lane adds
+// the Mloc of its column.  Each wavefront sums its own 64-column strip; the
+// sums leaving a strip's edge are kept per row in LDS and added to the
+// lines' values in the neighbouring strip when T is formed.  Rloc, Mloc,
+// la, lb stay within one tile and are kept in the local type; Stop, TAc,
+// TBc and the row-carry sum in the accumulator.
 template <typename St> struct Pair;
 template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
@@ -730,18 +690,22 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   typedef typename PT<P>::store St;
   typedef typename LocalT<P>::type Lc;
   constexpr int NW = TW / 64, SB = kSub_Rows;
-  constexpr int XW = TW + 2 * TH;          // columns x0-TH .. x0+TW+TH-1
   constexpr int NSL = TW + TH + 1;         // anti-diagonal / diagonal slots
+  constexpr int D = TW + TH - 1;           // line masses per tile in the reduce pass's table
+  constexpr int PP = TW + 4;               // row pitch of Pn (16-byte aligned rows)
+  constexpr int OP = 64 + TH;              // rows of the strip-edge tables, 64 leading zeros
+  static_assert(TH <= 64 && TH <= TW, "a line crosses at most one strip edge inside a tile row");
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);   // one block per tile of the batch
   int64_t first;
   const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
-  __shared__ __align__(16) Lc Pn[SB][TW];      // exclusive row prefix (from strip column TH) at node columns
-  __shared__ __align__(16) Lc Ml[SB][XW];      // Mloc of the sub-band's rows
-  __shared__ Lc la_s[SB][NSL];
-  __shared__ Lc lb_s[SB][NSL];
-  __shared__ A ca_s[NSL];                  // TAc - TBc pairs are formed from these
+  __shared__ __align__(16) Lc Pn[SB][PP];  // exclusive row prefix at node columns 0..TW (TW: the row total)
+  __shared__ Lc oa_s[NW + 1][OP];          // [w][64 + r]: anti-diagonal sum leaving strip w's left edge after row r
+  __shared__ Lc ob_s[NW + 1][OP];          // [w + 1][64 + r]: diagonal sum leaving strip w's right edge after row r
+  __shared__ Lc ea_s[TH];                  // right tile's mass below its anti-diagonal r
+  __shared__ Lc eb_s[TH];                  // left tile's line at its last column in row r: mass below - total
+  __shared__ A ca_s[NSL];
   __shared__ A cb_s[NSL];
   __shared__ A rc_s[TH];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -774,6 +738,19 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
         if (c0 + c < tx) run += v[c];
     }
     from_carry(rc_s[r], run);
+    // lines from the neighbouring tiles of this tile row (tile-local masses)
+    Lc ea = 0, eb = 0;
+    if (tx + 1 < L.ntx) ea = (Lc)agg[L.cdfA + ((int64_t)ty * L.ntx + tx + 1) * D + r];
+    if (tx > 0) {
+      const int64_t tl = (int64_t)ty * L.ntx + tx - 1;
+      eb = (Lc)(agg[L.cdfB + tl * D + (TW + TH - 2 - r)] - agg[L.tileTot + tl]);
+    }
+    ea_s[r] = ea;
+    eb_s[r] = eb;
+  }
+  for (int e = t; e < (NW + 1) * OP; e += TW) {   // rows before the tile row and the outer strips read 0
+    (&oa_s[0][0])[e] = (Lc)0;
+    (&ob_s[0][0])[e] = (Lc)0;
   }
   typedef typename Pair<St>::type St2;
   g_ptr<St> S = (g_ptr<St>)I.S;
@@ -800,10 +777,11 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
     }
   }
   St sv[SB], svN[SB];      // S of the sub-band's rows, stored with T (interleaved tables)
-  const int s1 = t + TW;
-  const bool has1 = s1 < NSL - 1;          // slot TW+TH serves node column N only: the extra thread's
+  Lc lav[SB], lbv[SB];     // strip sums of the lines through the sub-band's nodes
+  Lc laNv[SB];             // node column N: its anti-diagonal lies right of the texture
   A sb = stop, sbN = stopN;   // column carry plus the row carries of the rows done
-  Lc rsum = 0, rsumN = 0, la0 = 0, la1 = 0, lb0 = 0, lb1 = 0, laN = 0;
+  Lc rsum = 0, rsumN = 0, rpre = 0;
+  Lc ra = 0, rb = 0;       // shift registers: anti-diagonal through this column, diagonal arriving here
   // stores of whole rows: buffer stores, the row offset in a scalar register
   // (tables are below 2 GiB: checked on the host)
   const int64_t tab_bytes = (int64_t)(N + 1) * I.pitch * (IL ? (int64_t)sizeof(St2) : (int64_t)sizeof(St));
@@ -817,119 +795,114 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   // blocks per CU such stores wrote the new values (double-precision series
   // runs were not reproducible).
   constexpr bool kSplit = IL && sizeof(St) == 8;
-  // T of the rows of sub-band r0, from the slot sums of its sweep
+  // T of the rows of sub-band r0: carries, strip sums and the parts of the
+  // lines in the neighbouring strips (rows before the line entered)
   auto t_pass = [&](int r0) {
-    // rows without branches between them, so their LDS reads can be batched
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;   // j <= N: N is a multiple of TH
-      const int sa = t + r + 1, sb = t + TH - 1 - r;
-      A v = acc_sub(ca_s[sa], cb_s[sb]);
-      acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
+      const int sa = t + r + 1, sbl = t + TH - 1 - r;
+      A v = acc_sub(ca_s[sa], cb_s[sbl]);
+      const Lc la = lav[rr] + oa_s[w + 1][r + lane];       // row r - 64 + lane of strip w + 1
+      const Lc lb = lbv[rr] + ob_s[w][64 + r - lane];      // row r - lane of strip w - 1
+      acc_add_local(v, la - lb);
       if (kSplit) bstore((St)to_store(v), t_rs, i * (int)sizeof(St2) + (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St2)));
       else if (IL) bstore(St2{sv[rr], (St)to_store(v)}, t_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
       else bstore((St)to_store(v), t_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
     }
-    if (xcol) {
-      if (t == 0) {
+    if (extra) {
 #pragma unroll
-        for (int rr = 0; rr < SB; ++rr) {
-          const int r = r0 + rr;
-          const int64_t row = (int64_t)(y0 + r + 1) * pitch;
-          const int sa = TW + r + 1, sb = TW + TH - 1 - r;
-          A v = acc_sub(ca_s[sa], cb_s[sb]);
-          acc_add_local(v, la_s[rr][sa] - lb_s[rr][sb]);
-          if (kSplit) S[2 * (row + N) + 1] = (St)to_store(v);
-          else if (IL) ((g_ptr<St2>)I.S)[row + N] = St2{svN[rr], (St)to_store(v)};
-          else T[row + N] = to_store(v);
-        }
+      for (int rr = 0; rr < SB; ++rr) {
+        const int r = r0 + rr;
+        const int64_t row = (int64_t)(y0 + r + 1) * pitch;
+        A v = acc_sub(ca_s[TW + r + 1], cb_s[TW + TH - 1 - r]);
+        acc_add_local(v, laNv[rr] - ob_s[NW][64 + r]);   // diagonal: the last strip's edge sum
+        if (kSplit) S[2 * (row + N) + 1] = (St)to_store(v);
+        else if (IL) ((g_ptr<St2>)I.S)[row + N] = St2{svN[rr], (St)to_store(v)};
+        else T[row + N] = to_store(v);
       }
     }
   };
-  typedef RowStage<DENSE, XW, NW> Stage;
+  typedef RowStage<DENSE, TW, NW> Stage;
   Stage stg;
   stg.init(I);
   // pipeline: the labels of the sub-band after next and the densities
   // (table lookups) of the next one are in flight while a sub-band is done
-  float dnext[8];
-  stg.load(I, x0 - TH, y0);
+  float dnext[4];
+  stg.load(I, x0, y0);
   stg.values(I, dnext);
-  if (SB < TH) stg.load(I, x0 - TH, y0 + SB);
+  if (SB < TH) stg.load(I, x0, y0 + SB);
   for (int r0 = 0; r0 < TH; r0 += SB) {
-    // T of the previous sub-band; then this sub-band's densities and
-    // Mloc(c) = (row integral from strip column TH to c) + d(c)/2, each
-    // row scanned by one segment of a wavefront (8 columns per lane)
-    float dv[8];
+    // T of the previous sub-band; then this sub-band's exclusive row
+    // prefixes, each row scanned by one segment of a wavefront
+    float dv[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dv[e] = dnext[e];
+    for (int e = 0; e < 4; ++e) dv[e] = dnext[e];
     if (r0 + SB < TH) {
       stg.values(I, dnext);
-      if (r0 + 2 * SB < TH) stg.load(I, x0 - TH, y0 + r0 + 2 * SB);
+      if (r0 + 2 * SB < TH) stg.load(I, x0, y0 + r0 + 2 * SB);
     }
     if (r0 > 0) t_pass(r0 - SB);
     {
       Lc loc = 0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) loc += (Lc)dv[e];
-      const Lc x = seg_inclusive_scan_dpp<Stage::SEG>(loc);
-      const Lc ex = x - loc;                                  // exclusive prefix of the lane in its row
-      const int seg0 = lane - stg.li;
-      const Lc l0 = __shfl(ex, seg0 + TH / 8, 64);            // prefix at strip column TH (TH % 8 == 0)
-      if (stg.act) {
-        Lc run = ex - l0;
-        Lc mv[8], pv[8];
+      for (int e = 0; e < 4; ++e) loc += (Lc)dv[e];
+      const Lc x = seg_inclusive_scan_dpp<Stage::LPR>(loc);
+      Lc run = x - loc, pv[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          pv[e] = run;
-          mv[e] = run + (Lc)0.5 * (Lc)dv[e];
-          run += (Lc)dv[e];
-        }
-        const int c = 8 * stg.li;                 // chunks never straddle column TH or TH+TW
-        if (c >= TH && c < TH + TW) store8(&Pn[stg.g][c - TH], pv);
-        store8(&Ml[stg.g][c], mv);   // 16 B stores: lanes 32 B apart would conflict as scalars
+      for (int e = 0; e < 4; ++e) {
+        pv[e] = run;
+        run += (Lc)dv[e];
       }
+      store4(&Pn[stg.g][4 * stg.li], pv);
+      if (stg.li == Stage::LPR - 1) Pn[stg.g][TW] = x;   // the row total
     }
     __syncthreads();
 #pragma unroll
     for (int rr = 0; rr < SB; ++rr) {
       const int r = r0 + rr, j = y0 + r + 1;
+      const Lc p0 = Pn[rr][t], p1 = Pn[rr][t + 1];
+      const Lc m = (Lc)0.5 * (p0 + p1);                        // Mloc at this column
       acc_addv(sb, rc_s[r]);
-      rsum += Pn[rr][t];                                        // Rloc at node column i
+      rsum += p0;                                              // Rloc at node column i
       A v = sb;
       acc_add_local(v, rsum);
       sv[rr] = (St)to_store(v);
       if (!IL) bstore(sv[rr], s_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
       else if (kSplit) bstore(sv[rr], s_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
-      la0 += Ml[rr][t + TH - 1 - r];       // anti-diagonal slot t meets row y0+r here
-      lb0 += Ml[rr][t + r];                // diagonal slot t
-      la_s[rr][t] = la0;
-      lb_s[rr][t] = lb0;
+      // anti-diagonals move one lane left; the last strip's lane 63 takes
+      // the line arriving from the right tile (its part there: the row
+      // totals of the rows done plus the right tile's mass below it)
+      Lc ia = take_right(ra);
+      if (w == NW - 1) {
+        const Lc e = r > 0 ? rpre + ea_s[r - 1] : (Lc)0;
+        ia = lane == 63 ? e : ia;
+        rpre += Pn[rr][TW];
+      }
+      ra = ia + m;
+      if (lane == 0) oa_s[w][64 + r] = ra;
+      lav[rr] = ra;
+      // diagonals: the line at this column after row r, then one lane
+      // right; strip 0's lane 0 takes the line arriving from the left tile
+      const Lc z = rb + m;
+      if (lane == 63) ob_s[w + 1][64 + r] = z;
+      Lc ib = take_left(z);
+      if (w == 0) ib = lane == 0 ? eb_s[r] : ib;
+      rb = ib;
+      lbv[rr] = rb;
     }
-    if (has1) {                            // slots t + TW
+    if (extra) {
 #pragma unroll
       for (int rr = 0; rr < SB; ++rr) {
-        const int r = r0 + rr;
-        la1 += Ml[rr][s1 + TH - 1 - r];
-        lb1 += Ml[rr][s1 + r];
-        la_s[rr][s1] = la1;
-        lb_s[rr][s1] = lb1;
-      }
-    }
-    if (xcol) {
-      if (t == 0) {
-#pragma unroll
-        for (int rr = 0; rr < SB; ++rr) {
-          const int r = r0 + rr, j = y0 + r + 1;
-          acc_addv(sbN, rc_s[r]);
-          rsumN += Ml[rr][TW + TH];                             // column N lies outside: d = 0
-          laN += Ml[rr][TW + 2 * TH - 1 - r];                  // anti-diagonal slot TW+TH
-          la_s[rr][TW + TH] = laN;
-          A v = sbN;
-          acc_add_local(v, rsumN);
-          svN[rr] = (St)to_store(v);
-          if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
-          else if (kSplit) S[2 * ((int64_t)j * pitch + N)] = svN[rr];
-        }
+        const int r = r0 + rr, j = y0 + r + 1;
+        acc_addv(sbN, rc_s[r]);
+        rsumN += Pn[rr][TW];                                   // column N: the whole row lies left of it
+        laNv[rr] = rsumN;                                      // its anti-diagonal: the rows' totals
+        A v = sbN;
+        acc_add_local(v, rsumN);
+        svN[rr] = (St)to_store(v);
+        if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
+        else if (kSplit) S[2 * ((int64_t)j * pitch + N)] = svN[rr];
       }
     }
     __syncthreads();
