@@ -708,6 +708,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
   __shared__ A ca_s[NSL];
   __shared__ A cb_s[NSL];
   __shared__ A rc_s[TH];
+  __shared__ Lc laN_s[TH];                 // node column N: the rows' totals so far (its anti-diagonal)
+  __shared__ St sN_s[TH];                  // node column N: S, stored with T (interleaved float tables)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int N = I.N;
   const SatLayout L = sat_layout(N, TW, TH);
@@ -776,9 +778,8 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       }
     }
   }
-  St sv[SB], svN[SB];      // S of the sub-band's rows, stored with T (interleaved tables)
-  Lc lav[SB], lbv[SB];     // strip sums of the lines through the sub-band's nodes
-  Lc laNv[SB];             // node column N: its anti-diagonal lies right of the texture
+  St sv[SB];               // S of the sub-band's rows, stored with T (interleaved tables)
+  Lc dl[SB];               // strip sums of the lines through the sub-band's nodes: la - lb
   A sb = stop, sbN = stopN;   // column carry plus the row carries of the rows done
   Lc rsum = 0, rsumN = 0, rpre = 0;
   Lc ra = 0, rb = 0;       // shift registers: anti-diagonal through this column, diagonal arriving here
@@ -803,9 +804,9 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       const int r = r0 + rr, j = y0 + r + 1;   // j <= N: N is a multiple of TH
       const int sa = t + r + 1, sbl = t + TH - 1 - r;
       A v = acc_sub(ca_s[sa], cb_s[sbl]);
-      const Lc la = lav[rr] + oa_s[w + 1][r + lane];       // row r - 64 + lane of strip w + 1
-      const Lc lb = lbv[rr] + ob_s[w][64 + r - lane];      // row r - lane of strip w - 1
-      acc_add_local(v, la - lb);
+      // the lines' parts in the neighbouring strips: row r - 64 + lane of
+      // strip w + 1 (anti-diagonal), row r - lane of strip w - 1 (diagonal)
+      acc_add_local(v, dl[rr] + (oa_s[w + 1][r + lane] - ob_s[w][64 + r - lane]));
       if (kSplit) bstore((St)to_store(v), t_rs, i * (int)sizeof(St2) + (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St2)));
       else if (IL) bstore(St2{sv[rr], (St)to_store(v)}, t_rs, i * (int)sizeof(St2), (int)(j * pitch * (int64_t)sizeof(St2)));
       else bstore((St)to_store(v), t_rs, i * (int)sizeof(St), (int)(j * pitch * (int64_t)sizeof(St)));
@@ -816,9 +817,9 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
         const int r = r0 + rr;
         const int64_t row = (int64_t)(y0 + r + 1) * pitch;
         A v = acc_sub(ca_s[TW + r + 1], cb_s[TW + TH - 1 - r]);
-        acc_add_local(v, laNv[rr] - ob_s[NW][64 + r]);   // diagonal: the last strip's edge sum
+        acc_add_local(v, laN_s[r] - ob_s[NW][64 + r]);   // diagonal: the last strip's edge sum
         if (kSplit) S[2 * (row + N) + 1] = (St)to_store(v);
-        else if (IL) ((g_ptr<St2>)I.S)[row + N] = St2{svN[rr], (St)to_store(v)};
+        else if (IL) ((g_ptr<St2>)I.S)[row + N] = St2{sN_s[r], (St)to_store(v)};
         else T[row + N] = to_store(v);
       }
     }
@@ -881,7 +882,6 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       }
       ra = ia + m;
       if (lane == 0) oa_s[w][64 + r] = ra;
-      lav[rr] = ra;
       // diagonals: the line at this column after row r, then one lane
       // right; strip 0's lane 0 takes the line arriving from the left tile
       const Lc z = rb + m;
@@ -889,7 +889,7 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
       Lc ib = take_left(z);
       if (w == 0) ib = lane == 0 ? eb_s[r] : ib;
       rb = ib;
-      lbv[rr] = rb;
+      dl[rr] = ra - rb;
     }
     if (extra) {
 #pragma unroll
@@ -897,12 +897,13 @@ __global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
         const int r = r0 + rr, j = y0 + r + 1;
         acc_addv(sbN, rc_s[r]);
         rsumN += Pn[rr][TW];                                   // column N: the whole row lies left of it
-        laNv[rr] = rsumN;                                      // its anti-diagonal: the rows' totals
+        laN_s[r] = rsumN;                                      // its anti-diagonal: the rows' totals
         A v = sbN;
         acc_add_local(v, rsumN);
-        svN[rr] = (St)to_store(v);
-        if (!IL) S[(int64_t)j * pitch + N] = svN[rr];
-        else if (kSplit) S[2 * ((int64_t)j * pitch + N)] = svN[rr];
+        const St sN = (St)to_store(v);
+        if (!IL) S[(int64_t)j * pitch + N] = sN;
+        else if (kSplit) S[2 * ((int64_t)j * pitch + N)] = sN;
+        else sN_s[r] = sN;
       }
     }
     __syncthreads();
