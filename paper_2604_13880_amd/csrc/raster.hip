@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   if (inst_done(B, k)) return;
   constexpr int RPW = kFillRows / 4;   // rows per wavefront
   __shared__ uint64_t xs[4][kFillXing];
-  __shared__ uint64_t srt[4][kFillXing];
+  uint64_t (*const srt)[kFillXing] = xs;   // sorted in place: every lane holds its records before any is written
   __shared__ uint16_t sp_start[4][kFillXing + 2];
   __shared__ uint16_t sp_lab[4][kFillXing + 2];
   __shared__ uint32_t lcount[kLutLds];
@@ -268,7 +268,11 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       if (bad) cnt = 0;
       for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
     }
-    __syncthreads();
+    // Every LDS array of the row loop belongs to one wavefront, whose LDS
+    // accesses take effect in program order: no block barrier inside the
+    // loop (a row's wavefront never waits for the block's other rows), only
+    // a barrier against the compiler moving accesses across the phases.
+    __builtin_amdgcn_wave_barrier();
     cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)cnt);   // one row per wavefront
     if (row_ok) {
       // rank sort by the keys (p0, slot): every key is compared with all
@@ -281,23 +285,26 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
         for (uint32_t j = 0; j < cnt; ++j) rank += (uint32_t)__builtin_amdgcn_readlane((int)key, (int)j) < key;
         if (lane < (int)cnt) srt[w][rank] = rec;
       } else {
+        uint64_t rec[4];
         uint32_t key[4], rank[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const uint32_t i = (uint32_t)(lane + 64 * m);
-          key[m] = i < cnt ? (((uint32_t)(xs[w][i] & 0xFFFFull) << 8) | i) : ~0u;
+          rec[m] = i < cnt ? xs[w][i] : 0ull;
+          key[m] = i < cnt ? (((uint32_t)(rec[m] & 0xFFFFull) << 8) | i) : ~0u;
         }
         for (uint32_t j = 0; j < cnt; ++j) {
           const uint32_t kj = ((uint32_t)(xs[w][j] & 0xFFFFull) << 8) | j;
 #pragma unroll
           for (int m = 0; m < 4; ++m) rank[m] += kj < key[m];
         }
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          if ((uint32_t)(lane + 64 * m) < cnt) srt[w][rank[m]] = xs[w][lane + 64 * m];
+          if ((uint32_t)(lane + 64 * m) < cnt) srt[w][rank[m]] = rec[m];
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     if (row_ok) {
     uint32_t ngroups = 0;
     bool serial = false;     // the exact serial walk decides the row
@@ -630,8 +637,9 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       }
       if (lane == 0) I.row_cnt[q] = 0u;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
   // the block's counts into the instance totals (integer sums: order-independent)
   if (lds_counts)
     for (int v = t; v <= R; v += 256)
