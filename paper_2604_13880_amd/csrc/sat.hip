@@ -31,91 +31,8 @@ namespace cgk {
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// Staging of the densities of rows [y0, y0+SBR) x columns [xs, xs+W) into
-// LDS (zero outside the texture), split into a load (global -> registers)
-// and a store (registers -> LUT -> LDS) so that the next sub-band's loads
-// are in flight while the current one is processed.  W and xs are
-// multiples of 8 and N is a power of two >= 16, so every 8-wide chunk is
-// entirely inside or outside; a chunk is one 16-byte (labels) or two
-// 16-byte (density) loads.
-template <bool DENSE, int SBR, int W, int NT>
-struct Stager {
-  static constexpr int CH = W / 8;
-  static constexpr int NC = (SBR * CH + NT - 1) / NT;   // chunks per thread
-  static constexpr uint32_t kOut = 0x80000000u;         // buffer offset that reads 0
-  u32x4_t lab[NC];
-  f32x4_t da[DENSE ? NC : 1], db[DENSE ? NC : 1];
-  bool ok[NC];
-  __amdgpu_buffer_rsrc_t lab_rs, lut_rs;
-
-  __device__ __forceinline__ void init(const InstG& I) {
-    if (!DENSE) {
-      lab_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.labels, (short)0, (int)(2 * (int64_t)I.N * I.N), 0x00020000);
-      lut_rs = __builtin_amdgcn_make_buffer_rsrc((void*)I.lut, (short)0, 4 * I.n_lut, 0x00020000);
-    }
-  }
-
-  __device__ __forceinline__ void load(const InstG& I, int xs, int y0) {
-    const int N = I.N;
-#pragma unroll
-    for (int n = 0; n < NC; ++n) {
-      const int c = threadIdx.x + n * NT;
-      const int r = c / CH, k = c - r * CH;
-      const int q = y0 + r, p = xs + 8 * k;
-      ok[n] = c < SBR * CH && q < N && p >= 0 && p < N;
-      if (DENSE) {
-        if (ok[n]) {
-          const int64_t at = (int64_t)q * N + p;
-          da[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at);
-          db[DENSE ? n : 0] = *(g_ptr<const f32x4_t>)(I.density + at + 4);
-        }
-      } else {
-        const uint32_t off = ok[n] ? (uint32_t)(2 * ((int64_t)q * N + p)) : kOut;
-        lab[n] = __builtin_amdgcn_raw_buffer_load_b128(lab_rs, (int)off, 0, 0);
-      }
-    }
-  }
-
-  // Densities of the staged chunks into ds: LUT lookups from LDS (clamped
-  // index and a select) or by range-checked buffer loads; no branches.
-  __device__ __forceinline__ void store(const InstG& I, const float* lut_s, bool lut_lds, float (*ds)[W]) const {
-#pragma unroll
-    for (int n = 0; n < NC; ++n) {
-      const int c = threadIdx.x + n * NT;
-      if (c >= SBR * CH) break;
-      const int r = c / CH, k = c - r * CH;
-      float v[8];
-      if (DENSE) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          v[e] = ok[n] ? da[DENSE ? n : 0][e] : 0.f;
-          v[4 + e] = ok[n] ? db[DENSE ? n : 0][e] : 0.f;
-        }
-      } else if (lut_lds) {
-        const int nl = ok[n] ? I.n_lut : 0;   // outside the texture: no mass
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int lb = (int)((lab[n][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-          const float x = lut_s[lb < kLutLds ? lb : 0];
-          v[e] = lb < nl ? x : 0.f;   // labels outside the LUT carry no mass
-        }
-      } else {
-        const uint32_t out = ok[n] ? 0u : kOut;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t lb = (lab[n][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-          v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(lut_rs, (int)((lb << 2) | out), 0, 0));
-        }
-      }
-      *(f32x4_t*)&ds[r][8 * k] = f32x4_t{v[0], v[1], v[2], v[3]};
-      *(f32x4_t*)&ds[r][8 * k + 4] = f32x4_t{v[4], v[5], v[6], v[7]};
-    }
-  }
-};
-
 constexpr int kSub_Rows = 4;   // rows staged in LDS at a time (a sub-band of the tile)
 constexpr int kPrefLds = 1024;    // tile-row prefix totals the carry pass keeps in LDS
-constexpr int kReduce_Rows = 8;   // rows per sub-band of the reduce pass (every thread loads)
 
 __device__ __forceinline__ float shfl_xor_acc(float v, int d) { return __shfl_xor(v, d, 64); }
 __device__ __forceinline__ double shfl_xor_acc(double v, int d) { return __shfl_xor(v, d, 64); }
@@ -281,6 +198,16 @@ struct RowStage {
       lab = __builtin_amdgcn_raw_buffer_load_b64(lab_rs, (int)off, 0, 0);
     }
   }
+  // densities from a LUT copy in LDS (clamped index and a select)
+  __device__ __forceinline__ void values_lds(const float* lut_s, int n_lut, float v[4]) const {
+    const int nl = ok ? n_lut : 0;   // outside the texture: no mass
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int lb = (int)((lab[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+      const float x = lut_s[lb < kLutLds ? lb : 0];
+      v[e] = lb < nl ? x : 0.f;   // labels outside the LUT carry no mass
+    }
+  }
   __device__ __forceinline__ void values(const InstG& I, float v[4]) const {
     if (DENSE) {
 #pragma unroll
@@ -378,13 +305,18 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int k = find_inst(B, B.off_tiles, KD_TILES, b, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
-  constexpr int NW = TW / 64, D = TW + TH - 1, SB = (kReduce_Rows < TH ? kReduce_Rows : TH), E = TW / 64;
+  typedef typename LocalT<P>::type Lc;
+  typedef RowStage<DENSE, TW, TW / 64> Stage;
+  constexpr int NW = TW / 64, D = TW + TH - 1;
+  constexpr int LPR = Stage::LPR, NG = kSub_Rows;   // lanes per row; rows per step = row classes
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
-  static_assert(TH % SB == 0, "whole sub-bands");
-  __shared__ __align__(16) float ds[SB][TW];
+  static_assert(TH % NG == 0, "whole steps");
   __shared__ A rsum[TH];
   __shared__ A wt[NW];
   __shared__ float lut_s[kLutLds];
+  __shared__ Lc hpa[NG][D];    // line sums of one row class: anti-diagonals s = p + r
+  __shared__ Lc hpb[NG][D];    // diagonals s = p - r + TH - 1
+  __shared__ __align__(16) Lc colp[NG][TW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const SatLayout L = sat_layout(I.N, TW, TH);
   const int tile = (int)(b - first);
@@ -394,67 +326,93 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   if (!DENSE && B.make_lut) density_lut<TW>(I, lut_s, tile == 0);   // R + 1 <= kLutLds (host)
   else if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
-  typedef typename LocalT<P>::type Lc;
-  // Line sums by shift registers over each wavefront's 64-column strip:
-  // after row r, lane c of `sa` holds the strip's mass on the anti-diagonal
-  // through (c, r) above that row (it moves one lane left per row) and lane
-  // c of `sd` the mass on the diagonal (one lane right per row).  The sum
-  // leaving the strip at its left (anti-diagonal) or right (diagonal) edge
-  // after row r is complete; it is kept in lane r of oa / od.  The strips'
-  // partial line sums are added per tile afterwards.
-  constexpr int HP = 64 + TH - 1;           // line sums touching one strip
-  __shared__ Lc hpa[NW][HP];
-  __shared__ Lc hpb[NW][HP];
-  Lc col = 0, sa = 0, sd = 0, oa = 0, od = 0;
-  const int c1 = t + TW;
-  const bool has1 = c1 < D;
-  Stager<DENSE, SB, TW, TW> stg;
-  stg.init(I);
-  stg.load(I, x0, y0);
-  for (int r0 = 0; r0 < TH; r0 += SB) {
-    __syncthreads();
-    stg.store(I, lut_s, lut_lds, ds);
-    if (r0 + SB < TH) stg.load(I, x0, y0 + r0 + SB);   // next sub-band in flight
-    __syncthreads();
-    for (int rr = w; rr < SB; rr += NW) {   // row totals, one wavefront per row
-      Lc v = 0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v += (Lc)ds[rr][lane + 64 * e];
-      v = wave_inclusive_scan_dpp(v);       // lane 63 holds the row total
-      if (lane == 63) acc_zero(rsum[r0 + rr]), acc_add_local(rsum[r0 + rr], v);
-    }
-#pragma unroll
-    for (int rr = 0; rr < SB; ++rr) {
-      const int r = r0 + rr;
-      const Lc d = (Lc)ds[rr][t];
-      col += d;
-      if (r > 0) {
-        oa = lane_put(lane_get(sa, 0), r - 1, oa);    // anti-diagonal s = r - 1 of the strip
-        od = lane_put(lane_get(sd, 63), r - 1, od);   // diagonal s = TH + 63 - r of the strip
-      }
-      sa = d + take_right(sa);
-      sd = d + take_left(sd);
-    }
-  }
-  // strip partials: anti-diagonal s (c + r, strip columns) at hpa[s],
-  // diagonal s (c - r + TH - 1) at hpb[s]; then the tile's line sums,
-  // strips in order
-  hpa[w][lane + TH - 1] = sa;
-  hpb[w][lane] = sd;
-  if (lane < TH - 1) {
-    hpa[w][lane] = oa;
-    hpb[w][TH + 62 - lane] = od;
+  for (int e = t; e < NG * D; e += TW) {   // lines a row class never meets stay 0
+    (&hpa[0][0])[e] = (Lc)0;
+    (&hpb[0][0])[e] = (Lc)0;
   }
   __syncthreads();
-  auto line = [&](const Lc (*hp)[HP], int s) -> Lc {
+  // Every step covers NG rows: row r0 + g of the tile is held by one
+  // segment of LPR lanes, 4 consecutive columns per lane, so each lane
+  // sees every NG-th row of the same 4 columns.  Per lane and column it
+  // keeps the column sum of its rows and the sums of the anti-diagonal and
+  // the diagonal through that column: NG rows down, both lines have moved
+  // NG = 4 columns, i.e. one lane (DPP wave shift), left / right.  A line
+  // about to leave the tile is written to its row class's table; after the
+  // last step the lines still inside are.  No barrier inside the loop.
+  Stage stg;
+  stg.init(I);
+  const int g = stg.g, li = stg.li;
+  auto values = [&](float v[4]) {
+    if (lut_lds) stg.values_lds(lut_s, I.n_lut, v);
+    else stg.values(I, v);
+  };
+  Lc cs[4] = {0, 0, 0, 0}, la[4] = {0, 0, 0, 0}, lb[4] = {0, 0, 0, 0};
+  float dnext[4];
+  stg.load(I, x0, y0);
+  values(dnext);
+  if (NG < TH) stg.load(I, x0, y0 + NG);
+  for (int r0 = 0; r0 < TH; r0 += NG) {
+    const int r = r0 + g;
+    float dv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dv[e] = dnext[e];
+    if (r0 + NG < TH) {   // densities of the next step, labels of the one after
+      values(dnext);
+      if (r0 + 2 * NG < TH) stg.load(I, x0, y0 + r0 + 2 * NG);
+    }
+    Lc s4 = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s4 += (Lc)dv[e];
+    const Lc rt = seg_inclusive_scan_dpp<LPR>(s4);   // the segment's last lane: the row total
+    if (li == LPR - 1) {
+      acc_zero(rsum[r]);
+      acc_add_local(rsum[r], rt);
+    }
+    if (r0 > 0) {   // lines leaving at the left (anti-diagonal) or right (diagonal) edge
+      if (li == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) hpa[g][c + r - NG] = la[c];
+      }
+      if (li == LPR - 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) hpb[g][TW - 4 + c - (r - NG) + TH - 1] = lb[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      Lc ia = take_right(la[c]), ib = take_left(lb[c]);
+      if (LPR < 64) {   // segments hold different rows: new lines enter at the ends
+        ia = li == LPR - 1 ? (Lc)0 : ia;
+        ib = li == 0 ? (Lc)0 : ib;
+      }
+      la[c] = ia + (Lc)dv[c];
+      lb[c] = ib + (Lc)dv[c];
+      cs[c] += (Lc)dv[c];
+    }
+  }
+  {
+    const int rl = TH - NG + g;   // last row of this class
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      hpa[g][4 * li + c + rl] = la[c];
+      hpb[g][4 * li + c - rl + TH - 1] = lb[c];
+    }
+    store4(&colp[g][4 * li], cs);
+  }
+  __syncthreads();
+  // per thread: column t's total and the line sums of slots t and t + TW,
+  // row classes in order
+  Lc col = 0;
+#pragma unroll
+  for (int gg = 0; gg < NG; ++gg) col += colp[gg][t];
+  auto line = [&](const Lc (*hp)[D], int sl) -> Lc {
     Lc v = 0;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) {
-      const int o = s - 64 * ww;
-      if (o >= 0 && o < HP) v += hp[ww][o];
-    }
+    for (int gg = 0; gg < NG; ++gg) v += hp[gg][sl];
     return v;
   };
+  const int c1 = t + TW;
+  const bool has1 = c1 < D;
   const Lc ha0 = line(hpa, t), hb0 = line(hpb, t);
   const Lc ha1 = has1 ? line(hpa, c1) : (Lc)0, hb1 = has1 ? line(hpb, c1) : (Lc)0;
   __syncthreads();
