@@ -641,8 +641,12 @@ template <> struct Pair<double> { typedef double type __attribute__((ext_vector_
 // IL: S and T interleaved in one table of (S, T) pairs (the series driver's
 // own buffers: one store per node, and the mapping kernel gathers both
 // values of a node from one cache line); else two separate tables.
+// Occupancy: asked for 7 wavefronts per SIMD, the compensated mode fits
+// 64 registers (8 wavefronts, no spills: the uneven batch's writer 694 ->
+// 676 us); the double-accumulator mode does not (spills, slower), so it
+// keeps the compiler's choice.
 template <int P, int TW, int TH, bool DENSE, bool IL>
-__global__ __launch_bounds__(TW) void k_sat_final(Batch B) {
+__global__ __launch_bounds__(TW, P == CG_COMP ? 7 : 1) void k_sat_final(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
   typedef typename PT<P>::store St;
