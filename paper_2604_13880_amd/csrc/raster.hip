@@ -252,6 +252,14 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int q0 = (int)(blockIdx.x - first) * kFillRows;
   const bool lds_counts = (R + 1) <= kLutLds;
+  // the first row's crossing count and its bucket's first 64 slots are
+  // read together (the slots exist whatever the count)
+  uint32_t cnt_first = 0;
+  uint64_t rec_first = 0;
+  if (q0 + w * RPW < N) {
+    cnt_first = I.row_cnt[q0 + w * RPW];
+    rec_first = I.xing[(int64_t)(q0 + w * RPW) * kFillXing + lane];
+  }
   if (lds_counts)
     for (int v = t; v <= R; v += 256) lcount[v] = 0u;
   if (t == 0) contested_blk = 0ull;
@@ -262,11 +270,16 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
     uint32_t cnt = 0, off = 0;
     bool bad = false;
     if (row_ok) {
-      cnt = I.row_cnt[q];
+      cnt = rr == 0 ? cnt_first : I.row_cnt[q];
       off = (uint32_t)q * (uint32_t)kFillXing;
       if (cnt > (uint32_t)kFillXing) bad = true;
       if (bad) cnt = 0;
-      for (uint32_t i = lane; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
+      uint32_t i0 = lane;
+      if (rr == 0) {
+        if (lane < (int)cnt) xs[w][lane] = rec_first;
+        i0 += 64;
+      }
+      for (uint32_t i = i0; i < cnt; i += 64) xs[w][i] = I.xing[off + i];
     }
     // Every LDS array of the row loop belongs to one wavefront, whose LDS
     // accesses take effect in program order: no block barrier inside the

@@ -323,6 +323,9 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   const int tx = tile % L.ntx, ty = tile / L.ntx;
   const int x0 = tx * TW, y0 = ty * TH;
   const bool lut_lds = !DENSE && I.n_lut <= kLutLds;
+  Stage stg;
+  stg.init(I);
+  stg.load(I, x0, y0);   // the first labels are in flight while the density table is built
   if (!DENSE && B.make_lut) density_lut<TW>(I, lut_s, tile == 0);   // R + 1 <= kLutLds (host)
   else if (lut_lds)
     for (int v = t; v < I.n_lut; v += TW) lut_s[v] = I.lut[v];
@@ -339,8 +342,6 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   // NG = 4 columns, i.e. one lane (DPP wave shift), left / right.  A line
   // about to leave the tile is written to its row class's table; after the
   // last step the lines still inside are.  No barrier inside the loop.
-  Stage stg;
-  stg.init(I);
   const int g = stg.g, li = stg.li;
   auto values = [&](float v[4]) {
     if (lut_lds) stg.values_lds(lut_s, I.n_lut, v);
@@ -348,7 +349,6 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   };
   Lc cs[4] = {0, 0, 0, 0}, la[4] = {0, 0, 0, 0}, lb[4] = {0, 0, 0, 0};
   float dnext[4];
-  stg.load(I, x0, y0);
   values(dnext);
   if (NG < TH) stg.load(I, x0, y0 + NG);
   for (int r0 = 0; r0 < TH; r0 += NG) {
