@@ -306,11 +306,23 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
   const int t = threadIdx.x;
   double acc = 0.0;
   const int end = I.reg_pair_off[v];
-  for (int e = I.reg_pair_off[v - 1] + t; e < end; e += 256) {
-    typedef int i2 __attribute__((ext_vector_type(2)));
-    const i2 pr = *(g_ptr<const i2>)(I.reg_pairs + e);
-    const float2 a = ld2(I.xy + pr.x), b = ld2(I.xy + pr.y);
-    acc += (double)a.x * (double)b.y - (double)b.x * (double)a.y;
+  // four of the thread's edges per round: their loads are all in flight
+  // before the first is used (the terms are added in the same order)
+  constexpr int U = 4;
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  for (int e0 = I.reg_pair_off[v - 1] + t; e0 < end; e0 += 256 * U) {
+    i2 pr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pr[u] = e0 + 256 * u < end ? *(g_ptr<const i2>)(I.reg_pairs + e0 + 256 * u) : i2{0, 0};
+    float2 a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = ld2(I.xy + pr[u].x);
+      b[u] = ld2(I.xy + pr[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + 256 * u < end) acc += (double)a[u].x * (double)b[u].y - (double)b[u].x * (double)a[u].y;
   }
   acc = block_sum(acc, red);
   if (t == 0) I.areas[v] = 0.5 * acc;
@@ -329,10 +341,29 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   if (inst_done(B, k)) return;
   __shared__ double red[256];
   const int t = threadIdx.x, R = I.R;
+  g_ptr<IterState> st = I.st;
+  // the state the stopping rule reads (written by this kernel alone), loaded
+  // while the sums run
+  int32_t st_eval = 0, st_iter = 0, st_bestk = 0, st_flags = 0;
+  double st_best = 0.0;
+  if (t == 0 && mode == 0) {
+    st_eval = st->evaluated;
+    st_iter = st->iter;
+    st_bestk = st->best_k;
+    st_flags = st->flags;
+    st_best = st->best_xi;
+  }
   double sa = 0.0, ss = 0.0, bad = 0.0;
+  double A1 = 0.0;   // the thread's first region, kept for the second pass
+  float s1 = 0.f;
   for (int v = 1 + t; v <= R; v += 256) {
     const float s = I.values[v - 1];
-    sa += I.areas[v];
+    const double A = I.areas[v];
+    if (v == 1 + t) {
+      A1 = A;
+      s1 = s;
+    }
+    sa += A;
     ss += (double)s;
     bad = (s >= 0.f && s <= 3.4028235e38f) ? bad : 1.0;   // NaN, infinite or negative value
   }
@@ -341,8 +372,8 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   bad = block_max(bad, red);
   double se = 0.0, me = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double A = I.areas[v];
-    const double w = (double)I.values[v - 1] * sa / ss;
+    const double A = v == 1 + t ? A1 : I.areas[v];
+    const double w = (double)(v == 1 + t ? s1 : I.values[v - 1]) * sa / ss;
     const double m = fmax(A, w);
     const double e = m > 0.0 ? fabs(A - w) / m : 0.0;
     se += e;
@@ -351,7 +382,6 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   se = block_sum(se, red);
   me = block_max(me, red);
   if (t != 0) return;
-  g_ptr<IterState> st = I.st;
   const double xi = me, eps = R > 0 ? se / R : 0.0;
   I.areas[0] = 1.0 - sa;
   st->xi = xi;
@@ -374,29 +404,29 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   }
   if (mode == 4 && I.init_field != nullptr && st->ws_alpha == 0.f) st->flags |= CG_FLAG_FALLBACK;
   if (mode != 0) return;
-  int it;
-  if (!st->evaluated) {
+  int it, best_k = st_bestk;
+  if (!st_eval) {
     st->evaluated = 1;
     it = 0;
     st->best_xi = xi;
-    st->best_k = 0;
+    st->best_k = best_k = 0;
   } else {
-    it = st->iter + 1;
+    it = st_iter + 1;
     st->iter = it;
-    if (xi < st->best_xi) {
+    if (xi < st_best) {
       st->best_xi = xi;
-      st->best_k = it;
+      st->best_k = best_k = it;
     }
   }
   int done = 0, status = CG_STATUS_MAXITER;
   if (bad > 0.0 || !(ss > 0.0)) {   // the values define no density: nothing is iterated
-    st->flags |= CG_FLAG_BADVALUES;
+    st->flags = st_flags | CG_FLAG_BADVALUES;
     done = 1;
     status = CG_STATUS_ERROR;
-  } else if (st->flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
+  } else if (st_flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
   else if (I.fixed_iters > 0) { done = it >= I.fixed_iters; status = CG_STATUS_MAXITER; }
   else if (xi < (double)I.tol) { done = 1; status = CG_STATUS_CONVERGED; }
-  else if (it - st->best_k >= I.patience) { done = 1; status = CG_STATUS_STALLED; }
+  else if (it - best_k >= I.patience) { done = 1; status = CG_STATUS_STALLED; }
   else if (it >= I.max_iters) { done = 1; status = CG_STATUS_MAXITER; }
   st->status = status;
   st->done = done;

@@ -536,9 +536,16 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
     g_ptr<const Cy> ag = (g_ptr<const Cy>)I.agg;
     for (int ty = threadIdx.x; ty < L.nty; ty += 256) {
       Cy run = 0;
-      for (int tx = 0; tx < L.ntx; ++tx) {
-        pref_s[ty * (L.ntx + 1) + tx] = run;
-        run += ag[L.tileTot + (int64_t)ty * L.ntx + tx];
+      for (int c0 = 0; c0 < L.ntx; c0 += 8) {   // loads issued 8 at a time, summed in tile order
+        Cy v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = c0 + c < L.ntx ? ag[L.tileTot + (int64_t)ty * L.ntx + c0 + c] : (Cy)0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c0 + c < L.ntx) {
+            pref_s[ty * (L.ntx + 1) + c0 + c] = run;
+            run += v[c];
+          }
       }
       pref_s[ty * (L.ntx + 1) + L.ntx] = run;
     }
