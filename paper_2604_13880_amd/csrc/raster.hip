@@ -334,14 +334,46 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
       // (empty when xb = 0), after it the odd-multiplicity members of
       // {xb, ra, rb}; the xor label is exact iff at most one remains.  Rows
       // with several crossings at one p0 (a boundary wiggling inside one
-      // pixel: most rows of fractal maps) take the exact claim sets below.
+      // pixel: most rows of fractal maps) check whole groups: the claim set
+      // after a group is the one before it, {xb}, with the regions the
+      // group toggles an odd number of times flipped, so it stays a
+      // singleton (or empty) iff in the multiset {xb} + the group's region
+      // ids at most one id, the group's xor label, has an odd count.  Each
+      // lane counts its own ids and xb over its group (groups of up to 8
+      // crossings); rows that fail take the exact claim sets below.
       bool ok = !bad;
       const uint32_t pprev = wave_shr1(p0, 0u);
       const bool first = live && (lane == 0 || pprev != p0);
       if (__all(!last || first)) {
         if (last) ok = ok && single_claim_ok(x ^ ra ^ rb, ra, rb);
       } else {
-        ok = false;
+        constexpr int kMaxGroup = 8;
+        const uint64_t fm = __ballot(first), lm = __ballot(last);
+        const uint64_t below = fm & ((2ull << lane) - 1ull);   // lane 63: every bit
+        const uint64_t above = lm & ~((1ull << lane) - 1ull);
+        const int g0 = below ? 63 - __clzll((long long)below) : lane;   // the group's first and last crossing
+        const int g1 = above ? __ffsll((long long)above) - 1 : lane;
+        const uint32_t xb = __shfl(x ^ ra ^ rb, g0, 64);    // the label before the group
+        const uint32_t xa = __shfl(x, g1, 64);              // and after it
+        int gmax = live ? g1 - g0 + 1 : 0;
+        for (int o = 32; o >= 1; o >>= 1) gmax = max(gmax, __shfl_xor(gmax, o, 64));
+        if (gmax > kMaxGroup) {
+          ok = false;
+        } else {
+          uint32_t ca = xb == ra, cb = xb == rb, cx = 1u;   // counts of ra, rb and xb in the multiset
+          for (int d = 0; d < gmax; ++d) {
+            const int j = g0 + d;
+            const uint32_t raj = __shfl(ra, min(j, 63), 64), rbj = __shfl(rb, min(j, 63), 64);
+            if (j <= g1) {
+              ca += (raj == ra) + (rbj == ra);
+              cb += (raj == rb) + (rbj == rb);
+              cx += (raj == xb) + (rbj == xb);
+            }
+          }
+          // an id other than 0 has an odd count iff it is the label after the group
+          auto parity_ok = [&](uint32_t v, uint32_t c) { return v == 0u || ((v == xa) == ((c & 1u) != 0u)); };
+          ok = ok && (!live || (parity_ok(ra, ca) && parity_ok(rb, cb) && parity_ok(xb, cx)));
+        }
       }
       uint32_t label = x, nclaim = x != 0u;
       if (__any(!ok) && lds_counts) {
