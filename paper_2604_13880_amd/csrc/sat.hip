@@ -51,27 +51,38 @@ __device__ __forceinline__ A wave_sum(A v) {
   return v;
 }
 
-// Exclusive scan over the block's threads in thread order (fixed order);
-// `total` receives the block sum.  wt: LDS scratch of NW entries.
-template <typename A, int NW>
-__device__ __forceinline__ A block_exclusive_scan(A v, A* wt, A& total) {
+// K exclusive scans over the block's threads at once, each in thread order
+// (a fixed order; two barriers for all of them); `total` receives the
+// block sums.  wt: LDS scratch of K * NW entries.
+template <typename A, int NW, int K>
+__device__ __forceinline__ void block_exclusive_scans(A (&v)[K], A* wt, A (&total)[K]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const A ex = wave_exclusive_scan(v, lane);
-  A inc = ex;
-  acc_addv(inc, v);
-  __syncthreads();
-  if (lane == 63) wt[w] = inc;
-  __syncthreads();
-  A pre;
-  acc_zero(pre);
-  acc_zero(total);
+  A ex[K];
 #pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    if (i < w) acc_addv(pre, wt[i]);
-    acc_addv(total, wt[i]);
+  for (int k = 0; k < K; ++k) ex[k] = wave_exclusive_scan(v[k], lane);
+  __syncthreads();
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      A inc = ex[k];
+      acc_addv(inc, v[k]);
+      wt[k * NW + w] = inc;
+    }
   }
-  acc_addv(pre, ex);
-  return pre;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    A pre;
+    acc_zero(pre);
+    acc_zero(total[k]);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      if (i < w) acc_addv(pre, wt[k * NW + i]);
+      acc_addv(total[k], wt[k * NW + i]);
+    }
+    acc_addv(pre, ex[k]);
+    v[k] = pre;
+  }
 }
 
 // Local sums inside a tile (at most one tile row-strip of mass) use float
@@ -297,7 +308,7 @@ __device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool p
 }
 
 template <int P, int TW, int TH, bool DENSE>
-__global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
+__global__ __launch_bounds__(TW, 8) void k_sat_reduce(Batch B) {
   typedef typename PT<P>::acc A;
   typedef typename PT<P>::carry Cy;
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);   // one block per tile of the batch
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   static_assert(TH <= TW, "tiles are at least as wide as they are tall");
   static_assert(TH % NG == 0, "whole steps");
   __shared__ A rsum[TH];
-  __shared__ A wt[NW];
+  __shared__ A wt[5 * NW];
   __shared__ float lut_s[kLutLds];
   __shared__ Lc hpa[NG][D];    // line sums of one row class: anti-diagonals s = p + r
   __shared__ Lc hpb[NG][D];    // diagonals s = p - r + TH - 1
@@ -419,24 +430,23 @@ __global__ __launch_bounds__(TW) void k_sat_reduce(Batch B) {
   g_ptr<Cy> agg = (g_ptr<Cy>)I.agg;
   const int64_t tid = (int64_t)ty * L.ntx + tx;
   for (int r = t; r < TH; r += TW) agg[L.rowTot + (int64_t)tx * L.NY + y0 + r] = to_carry(rsum[r]);
-  A tot, tA0, tA1, tB0, tB1, z, colA, ha0A, ha1A, hb0A, hb1A;
+  A z, colA, ha0A, ha1A, hb0A, hb1A;
   acc_zero(z);
   acc_zero(colA); acc_add_local(colA, col);
   acc_zero(ha0A); acc_add_local(ha0A, ha0);
   acc_zero(ha1A); acc_add_local(ha1A, ha1);
   acc_zero(hb0A); acc_add_local(hb0A, hb0);
   acc_zero(hb1A); acc_add_local(hb1A, hb1);
-  A ex = block_exclusive_scan<A, NW>(colA, wt, tot);
+  // column prefix, and the line masses below every anti-diagonal / diagonal slot
+  A sc[5] = {colA, ha0A, has1 ? ha1A : z, hb0A, has1 ? hb1A : z}, stot[5];
+  block_exclusive_scans<A, NW, 5>(sc, wt, stot);
+  A ex = sc[0], tot = stot[0], ea0 = sc[1], tA0 = stot[1], ea1 = sc[2], eb0 = sc[3], tB0 = stot[3], eb1 = sc[4];
   acc_addv(ex, colA);
   agg[L.colsum + tid * (TW + 1) + t + 1] = to_carry(ex);
   if (t == 0) {
     agg[L.colsum + tid * (TW + 1)] = (Cy)0;
     agg[L.tileTot + tid] = to_carry(tot);
   }
-  A ea0 = block_exclusive_scan<A, NW>(ha0A, wt, tA0);
-  A ea1 = block_exclusive_scan<A, NW>(has1 ? ha1A : z, wt, tA1);
-  A eb0 = block_exclusive_scan<A, NW>(hb0A, wt, tB0);
-  A eb1 = block_exclusive_scan<A, NW>(has1 ? hb1A : z, wt, tB1);
   acc_addv(ea0, acc_half(ha0A));
   acc_addv(eb0, acc_half(hb0A));
   agg[L.cdfA + tid * D + t] = to_carry(ea0);

@@ -82,6 +82,28 @@ def test_rasterize_folded_map_and_ragged_sizes(ctx):
         np.testing.assert_array_equal(_np(cnt), wcnt)
 
 
+@pytest.mark.parametrize("noise", [0.0, 0.004])
+def test_rasterize_many_crossings_per_pixel(ctx, noise):
+    """A fractal map of ~5000 vertices on a 64^2 texture: most rows have
+    several crossings in one pixel (groups of coincident crossings); with
+    vertex noise the map folds, so some groups hold more than one claim
+    and the exact per-region claim sets decide.  Labels, counts and the
+    contested-pixel count bit for bit."""
+    m = voronoi_map(1700, 40, 5000, fractal=True)
+    rng = np.random.default_rng(17)
+    xy = np.clip(m.xy + noise * rng.standard_normal(m.xy.shape), 0.0, 1.0).astype(np.float32)
+    gm = ctx.map_from(m)
+    for N in (64, 128):
+        lab, cnt, cont = ctx.rasterize(gm, xy, N)
+        want, wcnt, wconf = oc.rasterize(xy.astype(np.float64), m.ring_off, m.ring_idx, m.ring_reg, m.n_regions, N)
+        say("noise", noise, "N", N, "contested", wconf)
+        if noise > 0:
+            assert wconf > 0
+        assert int(_np(cont)[0]) == wconf
+        np.testing.assert_array_equal(_labels_np(lab), want)
+        np.testing.assert_array_equal(_np(cnt), wcnt)
+
+
 def test_rasterize_deformed_map(ctx):
     # a map after several oracle iterations (vertices off any grid)
     m = voronoi_map(1002, 32, 2000, fractal=False)
