@@ -298,8 +298,9 @@ __device__ __forceinline__ A wave_exclusive_scan(A v, int lane) {
 }
 
 // XCD-aware block order: consecutive logical tiles land on the same XCD
-// (the hardware deals blocks round-robin over the 8 XCDs), so halo reads
-// of neighbouring tiles hit the same L2.
+// (the hardware deals blocks round-robin over the 8 XCDs), so what
+// neighbouring tiles share (adjacent segments of the same label rows, the
+// line masses the writer reads from the tiles beside it) stays in one L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
   constexpr int64_t X = 8;
   int64_t per = nblocks / X;

@@ -19,10 +19,12 @@
 //                 of the raw densities, no row scans)
 //   k_sat_carry1  row carries across tile columns, tile-row prefix totals
 //   k_sat_carry2  carries entering every tile row for S, TA, TB; HA, HB
-//   k_sat_final   per tile with a TH-column halo on each side: row prefix
-//                 sums staged in LDS, then a sweep down the tile's rows
-//                 that accumulates S, TA, TB in registers and writes one
-//                 row of S and T per step (coalesced stores)
+//   k_sat_final   per tile (its own labels only; the parts of the
+//                 tilted lines in the neighbouring tiles come from the
+//                 reduce pass's line masses): row prefix sums staged in
+//                 LDS, then a sweep down the tile's rows that accumulates
+//                 S and the line sums in registers and writes one row of
+//                 S and T per step (coalesced stores)
 // Accumulation precision: float, compensated float or double (PT<P>).
 #include "cg_dev.h"
 
