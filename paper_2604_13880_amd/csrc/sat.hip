@@ -495,9 +495,13 @@ __global__ __launch_bounds__(256) void k_sat_carry1(Batch B) {
 }
 
 // Mass of tile row ty on the anti-diagonal side u (tiles fully below u give
-// their totals through the tile-row prefix, at most two tiles are cut).
+// their totals through the tile-row prefix, at most two tiles are cut),
+// in two parts: the tile-row prefix entry (its index into the [tile row]
+// [ntx + 1] prefix table) and the one or two cut tiles' line masses (0
+// where a tile is not cut), so that the line masses can be loaded before
+// the prefix table is complete.  Likewise on the diagonal side v.
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const Cy* pref, const SatLayout& L, int ty, int64_t u) {
+__device__ __forceinline__ int band_a_parts(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t u, Cy& a1, Cy& a2) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(u - y0 - TW - TH + 2, TW);
@@ -505,14 +509,13 @@ __device__ __forceinline__ Cy band_a(g_ptr<const Cy> agg, const Cy* pref, const 
   int64_t khi = floordiv(u - y0, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
   const int64_t base = L.cdfA + (int64_t)ty * L.ntx * D;
-  Cy s = pref ? pref[(int64_t)ty * (L.ntx + 1) + klo] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
-  if (klo <= khi) s += agg[base + klo * D + (u - klo * TW - y0)];
-  if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (u - (klo + 1) * TW - y0)];
-  return s;
+  a1 = klo <= khi ? agg[base + klo * D + (u - klo * TW - y0)] : (Cy)0;
+  a2 = klo + 1 <= khi ? agg[base + (klo + 1) * D + (u - (klo + 1) * TW - y0)] : (Cy)0;
+  return ty * (L.ntx + 1) + (int)klo;
 }
 
 template <int TW, int TH, typename Cy>
-__device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const Cy* pref, const SatLayout& L, int ty, int64_t v) {
+__device__ __forceinline__ int band_b_parts(g_ptr<const Cy> agg, const SatLayout& L, int ty, int64_t v, Cy& a1, Cy& a2) {
   constexpr int D = TW + TH - 1;
   const int64_t y0 = (int64_t)ty * TH;
   int64_t klo = ceildiv(v + y0 - TW + 1, TW);
@@ -520,10 +523,9 @@ __device__ __forceinline__ Cy band_b(g_ptr<const Cy> agg, const Cy* pref, const 
   int64_t khi = floordiv(v + y0 + TH - 1, TW);
   if (khi > L.ntx - 1) khi = L.ntx - 1;
   const int64_t base = L.cdfB + (int64_t)ty * L.ntx * D;
-  Cy s = pref ? pref[(int64_t)ty * (L.ntx + 1) + klo] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + klo];
-  if (klo <= khi) s += agg[base + klo * D + (v - klo * TW + y0 + TH - 1)];
-  if (klo + 1 <= khi) s += agg[base + (klo + 1) * D + (v - (klo + 1) * TW + y0 + TH - 1)];
-  return s;
+  a1 = klo <= khi ? agg[base + klo * D + (v - klo * TW + y0 + TH - 1)] : (Cy)0;
+  a2 = klo + 1 <= khi ? agg[base + (klo + 1) * D + (v - (klo + 1) * TW + y0 + TH - 1)] : (Cy)0;
+  return ty * (L.ntx + 1) + (int)klo;
 }
 
 // Carries entering every tile row: for each index (node column i for S,
@@ -542,6 +544,38 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
   __shared__ Cy partC[256];
   __shared__ Cy pref_s[PREF_LDS ? kPrefLds : 1];
   const SatLayout L = sat_layout(I.N, TW, TH);
+  const int N = I.N, nty = L.nty;
+  const int CH = L.carry_ch, IPB = 256 / CH;
+  const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
+  const int64_t idx = (int64_t)(blockIdx.x - first) * IPB + j;
+  g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
+  g_ptr<Cy> carry = (g_ptr<Cy>)I.carry;
+  const int64_t nS = L.NX + 1;
+  const int seg = idx < nS ? 0 : (idx < nS + L.LA ? 1 : (idx < nS + L.LA + L.LB ? 2 : 3));
+  const int ty0 = ch * kCarryRows;
+  // the band values' tile parts first (they do not need the prefix table),
+  // then the tile-row prefix entries
+  int pidx[kCarryRows];
+  Cy a1[kCarryRows], a2[kCarryRows];
+#pragma unroll
+  for (int d = 0; d < kCarryRows; ++d) {
+    const int ty = ty0 + d;
+    pidx[d] = 0;
+    a1[d] = a2[d] = (Cy)0;
+    if (ty < nty) {
+      if (seg == 0) {
+        const int i = (int)idx;
+        int tx = i / TW;
+        if (tx > L.ntx - 1) tx = L.ntx - 1;
+        pidx[d] = ty * (L.ntx + 1) + tx;
+        a1[d] = agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + (i - tx * TW)];
+      } else if (seg == 1) {
+        pidx[d] = band_a_parts<TW, TH, Cy>(agg, L, ty, idx - nS - 1, a1[d], a2[d]);
+      } else if (seg == 2) {
+        pidx[d] = band_b_parts<TW, TH, Cy>(agg, L, ty, idx - nS - L.LA - L.NY, a1[d], a2[d]);
+      }
+    }
+  }
   if (PREF_LDS) {
     // tile-row prefix totals, one thread per tile row (the order of the
     // row-carry pass): nty <= 256 and nty (ntx + 1) <= kPrefLds here
@@ -563,35 +597,18 @@ __global__ __launch_bounds__(256) void k_sat_carry2(Batch B) {
     }
     __syncthreads();
   }
-  const Cy* pref = PREF_LDS ? pref_s : nullptr;
-  const int N = I.N, nty = L.nty;
-  const int CH = L.carry_ch, IPB = 256 / CH;
-  const int t = threadIdx.x, ch = t / IPB, j = t - ch * IPB;
-  const int64_t idx = (int64_t)(blockIdx.x - first) * IPB + j;
-  g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
-  g_ptr<Cy> carry = (g_ptr<Cy>)I.carry;
-  const int64_t nS = L.NX + 1;
-  const int seg = idx < nS ? 0 : (idx < nS + L.LA ? 1 : (idx < nS + L.LA + L.LB ? 2 : 3));
-  const int ty0 = ch * kCarryRows;
+  auto prefix = [&](int pi) -> Cy { return PREF_LDS ? pref_s[pi] : agg[L.prefTot + pi]; };
   Cy band[kCarryRows], tot[kCarryRows];
   Cy sum = 0, sumC = 0;
 #pragma unroll
   for (int d = 0; d < kCarryRows; ++d) {
     const int ty = ty0 + d;
     Cy v = 0, w = 0;
-    if (ty < nty) {
-      if (seg == 0) {
-        const int i = (int)idx;
-        int tx = i / TW;
-        if (tx > L.ntx - 1) tx = L.ntx - 1;
-        v = (PREF_LDS ? pref[ty * (L.ntx + 1) + tx] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + tx]) +
-            agg[L.colsum + ((int64_t)ty * L.ntx + tx) * (TW + 1) + (i - tx * TW)];
-      } else if (seg == 1) {
-        v = band_a<TW, TH, Cy>(agg, pref, L, ty, idx - nS - 1);
-      } else if (seg == 2) {
-        v = band_b<TW, TH, Cy>(agg, pref, L, ty, idx - nS - L.LA - L.NY);
-        w = PREF_LDS ? pref[ty * (L.ntx + 1) + L.ntx] : agg[L.prefTot + (int64_t)ty * (L.ntx + 1) + L.ntx];
-      }
+    if (ty < nty && seg < 3) {
+      v = prefix(pidx[d]);   // + the cut tiles, in the order of the band sums
+      v += a1[d];
+      v += a2[d];
+      if (seg == 2) w = prefix(ty * (L.ntx + 1) + L.ntx);
     }
     band[d] = v;
     tot[d] = w;
