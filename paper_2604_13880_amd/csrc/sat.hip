@@ -720,6 +720,10 @@ __global__ __launch_bounds__(TW, P == CG_COMP ? 7 : 1) void k_sat_final(Batch B)
   const int x0 = tx * TW, y0 = ty * TH;
   g_ptr<const Cy> agg = (g_ptr<const Cy>)I.agg;
   g_ptr<const Cy> carry = (g_ptr<const Cy>)I.carry;
+  typedef RowStage<DENSE, TW, NW> Stage;
+  Stage stg;
+  stg.init(I);
+  stg.load(I, x0, y0);   // the first labels are in flight during the set-up
   // carries entering the tile
   A stop, stopN;
   from_carry(stop, carry[L.Stop + (int64_t)ty * (L.NX + 1) + x0 + t]);
@@ -826,13 +830,9 @@ __global__ __launch_bounds__(TW, P == CG_COMP ? 7 : 1) void k_sat_final(Batch B)
       }
     }
   };
-  typedef RowStage<DENSE, TW, NW> Stage;
-  Stage stg;
-  stg.init(I);
   // pipeline: the labels of the sub-band after next and the densities
   // (table lookups) of the next one are in flight while a sub-band is done
   float dnext[4];
-  stg.load(I, x0, y0);
   stg.values(I, dnext);
   if (SB < TH) stg.load(I, x0, y0 + SB);
   // Per sub-band: the exclusive row prefixes into LDS, a barrier, the
