@@ -152,6 +152,139 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution for C_in % 32 == 0 when a block's 256 pixels are
+// whole rows of one image (W a power of two, 16 <= W <= 128, H W a
+// multiple of 256).  For every 32 input channels the block stages in LDS
+// its rows plus a one-pixel border ((256/W + 2) x (W + 2) pixels, zeros
+// outside the image, 64 bytes per pixel) and the weights of its output
+// channels for all nine taps; the taps then read their A and B fragments
+// from LDS (B at shifted offsets), so each input pixel is fetched once per
+// block and channel chunk instead of once per tap, and the matrix cores
+// wait on one round of global loads per chunk (all issued together)
+// instead of one per tap and fragment.
+constexpr int conv_rows_pix(int W) { return (256 / W + 2) * (W + 2); }
+constexpr int kConvRowsMaxPix = conv_rows_pix(128) > conv_rows_pix(16) ? conv_rows_pix(128) : conv_rows_pix(16);
+static_assert(conv_rows_pix(32) <= kConvRowsMaxPix && conv_rows_pix(64) <= kConvRowsMaxPix, "LDS tile bound");
+
+bool conv3_rows_ok(int Cin, int64_t P, int H, int W) {
+  (void)P;
+  return Cin % 32 == 0 && W >= 16 && W <= 128 && (W & (W - 1)) == 0 && ((int64_t)H * W) % 256 == 0;
+}
+
+template <int MF, bool F32OUT>
+__global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__ in, int Cin,
+                                                    const uint16_t* __restrict__ wA, const float* __restrict__ bias,
+                                                    void* __restrict__ out, int Cout, int64_t P, int H, int W,
+                                                    int relu) {
+  constexpr int NF = 4;
+  constexpr int NA = 9 * 16 * MF * 4;                          // 16-byte pieces of the chunk's weights
+  constexpr int HALO_IT = (kConvRowsMaxPix * 4 + 255) / 256;    // pieces per thread
+  constexpr int A_IT = (NA + 255) / 256;
+  __shared__ __align__(16) uint16_t tile[kConvRowsMaxPix * 32];   // [pixel][32 channels]
+  __shared__ __align__(16) uint16_t wl[9 * 16 * MF * 32];        // [tap][output channel][32 channels]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int kq = lane >> 4, lr = lane & 15;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;   // first pixel of the block (whole rows, P % 256 == 0)
+  const int co0 = blockIdx.y * (16 * MF);
+  const int K = 9 * Cin;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t img = p0 / HW;
+  const int y0 = (int)((p0 - img * HW) / W);
+  const int RB = 256 / W, Wp = W + 2;                   // rows of the block, padded row length
+  const int npix = (RB + 2) * Wp;
+  const uint16_t* src0 = in + img * HW * Cin;
+  // this lane's four pixels (local index wv*64 + 16f + lr): LDS pixel of tap (0, 0)
+  int base[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int li = wv * 64 + 16 * f + lr;
+    const int r = li / W, c = li - r * W;   // W is a power of two
+    base[f] = (r + 1) * Wp + (c + 1);
+  }
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int m = 0; m < MF; ++m)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
+    // every load of the chunk in flight before any is stored: unconditional
+    // loads from clamped addresses, zeroed afterwards where outside
+    u32x4 hv[HALO_IT], av[A_IT];
+    bool hok[HALO_IT];
+#pragma unroll
+    for (int i = 0; i < HALO_IT; ++i) {
+      const int e = t + 256 * i;
+      const int pix = e >> 2, j = e & 3;
+      const int ty = pix / Wp, tx = pix - ty * Wp;
+      const int yy = y0 - 1 + ty, xx = tx - 1;
+      hok[i] = e < npix * 4 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const int64_t off = hok[i] ? ((int64_t)yy * W + xx) * Cin + c0 + 8 * j : 0;
+      hv[i] = *(const u32x4*)(src0 + off);
+    }
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int e = min(t + 256 * i, NA - 1);
+      const int tap = e / (64 * MF), row = (e >> 2) & (16 * MF - 1), j = e & 3;
+      av[i] = *(const u32x4*)(wA + (int64_t)(co0 + row) * K + tap * Cin + c0 + 8 * j);
+    }
+#pragma unroll
+    for (int i = 0; i < HALO_IT; ++i)
+      if (!hok[i]) hv[i] = u32x4{0u, 0u, 0u, 0u};
+    __syncthreads();   // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int i = 0; i < HALO_IT; ++i) {
+      const int e = t + 256 * i;
+      if (e < npix * 4) *(u32x4*)(tile + (e >> 2) * 32 + 8 * (e & 3)) = hv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int e = t + 256 * i;
+      if (e < NA) *(u32x4*)(wl + e * 8) = av[i];   // piece e: tap, row, j in that order
+    }
+    __syncthreads();
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+      const int off = (tap / 3 - 1) * Wp + (tap % 3 - 1);
+      bf16x8 a[MF], bb[NF];
+#pragma unroll
+      for (int m = 0; m < MF; ++m) a[m] = load8(wl + ((tap * 16 * MF + 16 * m + lr) * 32 + 8 * kq));
+#pragma unroll
+      for (int f = 0; f < NF; ++f) bb[f] = load8(tile + (base[f] + off) * 32 + 8 * kq);
+#pragma unroll
+      for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          acc[m][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[f], acc[m][f], 0, 0, 0);
+    }
+  }
+  // lane holds D[o = 4 kq + r][pixel = lr] of every fragment
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int64_t p = p0 + wv * 64 + 16 * f + lr;
+#pragma unroll
+    for (int m = 0; m < MF; ++m) {
+      const int o = co0 + 16 * m + 4 * kq;
+      f32x4 v4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[m][f][r] + (bias ? bias[o + r] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        v4[r] = v;
+      }
+      if (F32OUT) {
+        *(f32x4*)((float*)out + p * Cout + o) = v4;
+      } else {
+        u16x4 tv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[r] = f2bf(v4[r]);
+        *(u16x4*)((uint16_t*)out + p * Cout + o) = tv;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient dW[o][k] += sum_p g[p][o] * patch(in)[p][k].
 // Block: 32 output channels x 128 columns of K, 4 wavefronts each owning 32
 // columns; pixels in steps of 32 staged in LDS transposed ([channel][pixel]);
@@ -591,6 +724,15 @@ static void conv3_t(const uint16_t* in, int Cin, const uint16_t* wA, const float
   const int64_t P = (int64_t)Bn * H * W;
   const unsigned gx = (unsigned)((P + 255) / 256);
   const bool gen = Cin % 32 != 0;
+  if (conv3_rows_ok(Cin, P, H, W)) {   // whole rows per block: P is a multiple of 256
+    if (Cout % 64 == 0)
+      hipLaunchKernelGGL((k_conv3_rows<4, F32OUT>), dim3(gx, Cout / 64), dim3(256), 0, s, in, Cin, wA, bias, out, Cout,
+                         P, H, W, relu);
+    else
+      hipLaunchKernelGGL((k_conv3_rows<2, F32OUT>), dim3(gx, Cout / 32), dim3(256), 0, s, in, Cin, wA, bias, out, Cout,
+                         P, H, W, relu);
+    return;
+  }
   if (Cout % 64 == 0) {
     dim3 grid(gx, Cout / 64);
     if (gen) hipLaunchKernelGGL((k_conv3<4, true, F32OUT>), grid, dim3(256), 0, s, in, Cin, wA, bias, out, Cout, P, H, W, relu);
