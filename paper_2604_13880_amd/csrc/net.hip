@@ -61,6 +61,11 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
   for (int m = 0; m < MF; ++m)
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // this lane's biases (output channels co0 + 16 m + 4 kq + r), read once
+  f32x4 bv[MF];
+#pragma unroll
+  for (int m = 0; m < MF; ++m)
+    bv[m] = bias ? *(const f32x4*)(bias + co0 + 16 * m + 4 * kq) : f32x4{0.f, 0.f, 0.f, 0.f};
 
   if (!GEN) {
     for (int tap = 0; tap < 9; ++tap) {
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
       f32x4 v4;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = acc[m][f][r] + (bias ? bias[o + r] : 0.f);
+        float v = acc[m][f][r] + bv[m][r];
         if (relu) v = fmaxf(v, 0.f);
         v4[r] = v;
       }
@@ -206,12 +211,18 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
   for (int m = 0; m < MF; ++m)
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // this lane's biases (output channels co0 + 16 m + 4 kq + r), read once
+  f32x4 bv[MF];
+#pragma unroll
+  for (int m = 0; m < MF; ++m)
+    bv[m] = bias ? *(const f32x4*)(bias + co0 + 16 * m + 4 * kq) : f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int c0 = 0; c0 < Cin; c0 += 32) {
-    // every load of the chunk in flight before any is stored: unconditional
-    // loads from clamped addresses, zeroed afterwards where outside
-    u32x4 hv[HALO_IT], av[A_IT];
-    bool hok[HALO_IT];
+  // every load of a chunk in flight together, the next chunk's during
+  // this one's products: unconditional loads from clamped addresses,
+  // zeroed where outside the image
+  u32x4 hv[HALO_IT], av[A_IT];
+  bool hok[HALO_IT];
+  auto issue = [&](int c0) {
 #pragma unroll
     for (int i = 0; i < HALO_IT; ++i) {
       const int e = t + 256 * i;
@@ -228,14 +239,14 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
       const int tap = e / (64 * MF), row = (e >> 2) & (16 * MF - 1), j = e & 3;
       av[i] = *(const u32x4*)(wA + (int64_t)(co0 + row) * K + tap * Cin + c0 + 8 * j);
     }
-#pragma unroll
-    for (int i = 0; i < HALO_IT; ++i)
-      if (!hok[i]) hv[i] = u32x4{0u, 0u, 0u, 0u};
+  };
+  issue(0);
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
     __syncthreads();   // the previous chunk's LDS reads are done
 #pragma unroll
     for (int i = 0; i < HALO_IT; ++i) {
       const int e = t + 256 * i;
-      if (e < npix * 4) *(u32x4*)(tile + (e >> 2) * 32 + 8 * (e & 3)) = hv[i];
+      if (e < npix * 4) *(u32x4*)(tile + (e >> 2) * 32 + 8 * (e & 3)) = hok[i] ? hv[i] : u32x4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int i = 0; i < A_IT; ++i) {
@@ -243,6 +254,7 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
       if (e < NA) *(u32x4*)(wl + e * 8) = av[i];   // piece e: tap, row, j in that order
     }
     __syncthreads();
+    if (c0 + 32 < Cin) issue(c0 + 32);
 #pragma unroll 3
     for (int tap = 0; tap < 9; ++tap) {
       const int off = (tap / 3 - 1) * Wp + (tap % 3 - 1);
@@ -268,7 +280,7 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
       f32x4 v4;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = acc[m][f][r] + (bias ? bias[o + r] : 0.f);
+        float v = acc[m][f][r] + bv[m][r];
         if (relu) v = fmaxf(v, 0.f);
         v4[r] = v;
       }
