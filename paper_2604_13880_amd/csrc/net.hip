@@ -94,6 +94,8 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
     }
   } else {
     for (int k0 = 0; k0 < K; k0 += 32) {
+      // element gathers from clamped addresses (all in flight together),
+      // zeroed afterwards where k or the tap's pixel is outside
       bf16x8 a[MF], bb[NF];
 #pragma unroll
       for (int m = 0; m < MF; ++m) {
@@ -102,7 +104,8 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int k = k0 + 8 * kq + e;
-          tv[e] = k < K ? wr[k] : (uint16_t)0;
+          const uint16_t v = wr[k < K ? k : 0];
+          tv[e] = k < K ? v : (uint16_t)0;
         }
         a[m] = __builtin_bit_cast(bf16x8, tv);
       }
@@ -112,13 +115,11 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, 
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int k = k0 + 8 * kq + e;
-          uint16_t v = 0;
-          if (k < K && pv[f]) {
-            const int tap = k / Cin, c = k - tap * Cin;
-            const int yy = py[f] + tap / 3 - 1, xx = pxx[f] + tap % 3 - 1;
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = in[(pimg[f] + (int64_t)yy * W + xx) * Cin + c];
-          }
-          tv[e] = v;
+          const int tap = k / Cin, c = k - tap * Cin;
+          const int yy = py[f] + tap / 3 - 1, xx = pxx[f] + tap % 3 - 1;
+          const bool ok = k < K && pv[f] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+          const uint16_t v = in[ok ? (pimg[f] + (int64_t)yy * W + xx) * Cin + c : 0];
+          tv[e] = ok ? v : (uint16_t)0;
         }
         bb[f] = __builtin_bit_cast(bf16x8, tv);
       }
