@@ -670,7 +670,8 @@ def main():
     ap.add_argument("--learned-maps", type=int, default=64, help="held-out maps of the learned comparison")
     ap.add_argument("--parts", default="main,series,uneven,learned,forms,cpu",
                     help="comma list of main (the timed 1024^2 workload), series, uneven, learned, forms, cpu; "
-                         "profiling runs select one (the JSON line then holds null for the rest)")
+                         "profiling runs select one (the JSON line then holds null for the rest); 'net' alone "
+                         "prints only the warm-start net's forward and training-step throughput")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates the HBM traffic counters)")
     a = ap.parse_args()
@@ -693,6 +694,12 @@ def main():
     from synth import lognormal_values, voronoi_map
 
     parts = set(a.parts.split(","))
+    if parts == {"net"}:
+        from paper_2604_13880_amd import learned as Lr
+        ctx = B.Context(0)
+        print(json.dumps({"net": net_throughput(B, ctx, Lr.NET_CFG, torch)}))
+        ctx.close()
+        return
     if "main" not in parts:
         a.steps = 0
     w = WORKLOADS[a.workload]

@@ -569,9 +569,21 @@ __global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ g, 
   for (int cbase = 0; cbase < C; cbase += lanes_per_px) {
     const int c = cbase + t % lanes_per_px, row = t / lanes_per_px;
     const bool act = row < rows && c < C;
-    float s = 0.f;
-    if (act)
-      for (int64_t p = pbeg + row; p < pend; p += rows) s += bf2f(actv[p * C + c]) > 0.f ? g[p * C + c] : 0.f;
+    // four independent running sums (their loads in flight together),
+    // combined in a fixed order
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (act) {
+      int64_t p = pbeg + row;
+      for (; p + 3 * rows < pend; p += 4 * rows) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = p + u * rows;
+          s4[u] += bf2f(actv[q * C + c]) > 0.f ? g[q * C + c] : 0.f;
+        }
+      }
+      for (; p < pend; p += rows) s4[0] += bf2f(actv[p * C + c]) > 0.f ? g[p * C + c] : 0.f;
+    }
+    float s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     red[t] = s;
     __syncthreads();
     if (row == 0 && act) {
@@ -825,7 +837,7 @@ void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, f
 }
 // Blocks of the bias gradient (at most 256, at least 64 pixels each).
 int64_t bias_blocks(int64_t P, int64_t* px_per_block) {
-  int64_t blocks = 256;
+  int64_t blocks = 512;
   int64_t ppb = (P + blocks - 1) / blocks;
   if (ppb < 64) ppb = 64;
   if (px_per_block) *px_per_block = ppb;
