@@ -47,7 +47,7 @@ typedef struct {
   int32_t base_channels; /* channels of level 0; a multiple of 32 */
   int32_t levels;        /* 2..5 */
   int32_t height, width; /* input size; multiples of 2^(levels-1) */
-  int32_t max_batch;     /* largest batch passed to forward / backward */
+  int32_t max_batch;     /* largest batch passed to forward / backward; max_batch x height x width < 2^24 */
   float out_scale;       /* head output multiplier */
   uint64_t seed;         /* weight initialisation (He normal, zero biases) */
   int32_t in_channels;   /* input channels, 1..8 */

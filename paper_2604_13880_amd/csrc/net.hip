@@ -300,11 +300,20 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
 // ---------------------------------------------------------------------------
 // Weight gradient dW[o][k] += sum_p g[p][o] * patch(in)[p][k].
 // Block: 32 output channels x 128 columns of K, 4 wavefronts each owning 32
-// columns; pixels in steps of 32 staged in LDS transposed ([channel][pixel]);
+// columns; pixels in steps of kWgPix staged in LDS transposed ([channel][pixel]);
 // every block stores its partial sums for its share of the pixels
 // (blockIdx.z) in part[z][o][k]; k_sum_parts adds the shares to the
 // gradient in a fixed order, so the result does not depend on scheduling.
-constexpr int kWgPix = 32;
+// n = q d + r for 0 <= n < 2^24 and d >= 1, from a float reciprocal
+// corrected by one step (the float quotient is off by at most one there).
+__device__ __forceinline__ void divmod24(int n, int d, float inv, int& q, int& r) {
+  q = (int)((float)n * inv);
+  r = n - q * d;
+  q = r < 0 ? q - 1 : (r >= d ? q + 1 : q);
+  r = n - q * d;
+}
+
+constexpr int kWgPix = 64;
 constexpr int kWgPad = kWgPix + 8;   // row pitch in LDS (elements)
 
 template <bool GEN>
@@ -327,55 +336,88 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int f = 0; f < 2; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t p0 = pbeg; p0 < pend; p0 += kWgPix) {
-    __syncthreads();
-    // g tile: 32 pixels x 32 channels = 128 chunks of 8 channels
-    if (t < 128) {
+  // Per step of kWgPix pixels: the g tile (pixels x 32 channels, one chunk
+  // of 8 channels per thread) and the patch tile (pixels x 128 columns of
+  // K, four chunks of 8 columns per thread, C_in % 8 == 0) are loaded from
+  // clamped addresses, the next step's while this one's products run, and
+  // written to LDS transposed so that pixels are the reduction axis.
+  constexpr int NB = kWgPix * 16 / 256;
+  u16x8 gv, bv[NB];
+  bool gok, bok[NB];
+  // pixel -> (row, column) by float reciprocals (P < 2^24, checked on the
+  // host); this thread's columns of K, hence its tap, are fixed
+  const int HWi = H * W;
+  const float inv_hw = 1.f / (float)HWi, inv_w = 1.f / (float)W;
+  const int kk_t = (t & 15) * 8, k_t = k0 + kk_t;
+  const int tap_t = k_t / Cin, ci_t = k_t - tap_t * Cin;
+  const int dy_t = tap_t / 3 - 1, dx_t = tap_t % 3 - 1;
+  const bool kok_t = k_t < K;
+  auto issue = [&](int64_t p0) {
+    {
       const int pi = t >> 2, cc = (t & 3) * 8;
       const int64_t p = p0 + pi;
-      u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (p < pend) v = *(const u16x8*)(g + p * Cout + o0 + cc);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) As[cc + e][pi] = v[e];
+      gok = p < pend;
+      gv = *(const u16x8*)(g + (gok ? p * Cout + o0 + cc : 0));
     }
-    // patch tile: 32 pixels x 128 columns of K
-    if (!GEN) {
-      for (int c = t; c < kWgPix * 16; c += 256) {
-        const int pi = c >> 4, kk = (c & 15) * 8;
-        const int64_t p = p0 + pi;
-        const int k = k0 + kk;
-        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        bool ok = p < pend && k < K;
-        int64_t at = 0;
-        if (ok) {
-          const int tap = k / Cin, ci = k - tap * Cin;
-          const int64_t b = p / HW, rem = p - b * HW;
-          const int y = (int)(rem / W), x = (int)(rem - (int64_t)y * W);
-          const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-          ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-          at = (b * HW + (int64_t)yy * W + xx) * Cin + ci;
-        }
-        if (ok) v = *(const u16x8*)(in + at);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[kk + e][pi] = v[e];
+    for (int i = 0; i < NB; ++i) {
+      const int p = (int)p0 + (t >> 4) + 16 * i;
+      int b, rem, y, x;
+      divmod24(p, HWi, inv_hw, b, rem);
+      divmod24(rem, W, inv_w, y, x);
+      const int yy = y + dy_t, xx = x + dx_t;
+      bok[i] = p < pend && kok_t && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      bv[i] = *(const u16x8*)(in + (bok[i] ? ((int64_t)p + dy_t * W + dx_t) * Cin + ci_t : 0));
+    }
+  };
+  if (!GEN) issue(pbeg);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kWgPix) {
+    __syncthreads();
+    if (!GEN) {
+      {
+        const int pi = t >> 2, cc = (t & 3) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[cc + e][pi] = gok ? gv[e] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int c = t + 256 * i;
+        const int pi = c >> 4, kk = (c & 15) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[kk + e][pi] = bok[i] ? bv[i][e] : (uint16_t)0;
       }
     } else {
-      for (int c = t; c < kWgPix * 128; c += 256) {
-        const int pi = c >> 7, kk = c & 127;
+      // g tile as above; patch element by element (any C_in)
+      {
+        const int pi = t >> 2, cc = (t & 3) * 8;
         const int64_t p = p0 + pi;
-        const int k = k0 + kk;
-        uint16_t v = 0;
-        if (p < pend && k < K) {
-          const int tap = k / Cin, ci = k - tap * Cin;
-          const int64_t b = p / HW, rem = p - b * HW;
-          const int y = (int)(rem / W), x = (int)(rem - (int64_t)y * W);
-          const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-          if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = in[(b * HW + (int64_t)yy * W + xx) * Cin + ci];
-        }
-        Bs[kk][pi] = v;
+        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (p < pend) v = *(const u16x8*)(g + p * Cout + o0 + cc);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[cc + e][pi] = v[e];
       }
+      // this thread's column of K (c & 127 = t & 127) and tap are fixed
+      const int kk = t & 127, k = k0 + kk;
+      const int tap = k / Cin, ci = k - tap * Cin;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      constexpr int NE = kWgPix * 128 / 256;
+      uint16_t ev[NE];
+#pragma unroll
+      for (int j = 0; j < NE; ++j) {
+        const int p = (int)p0 + (t >> 7) + 2 * j;
+        int b, rem, y, x;
+        divmod24(p, HWi, inv_hw, b, rem);
+        divmod24(rem, W, inv_w, y, x);
+        const int yy = y + dy, xx = x + dx;
+        const bool ok = p < pend && k < K && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const uint16_t v = in[ok ? ((int64_t)p + dy * W + dx) * Cin + ci : 0];
+        ev[j] = ok ? v : (uint16_t)0;
+      }
+#pragma unroll
+      for (int j = 0; j < NE; ++j) Bs[kk][(t >> 7) + 2 * j] = ev[j];
     }
     __syncthreads();
+    if (!GEN && p0 + kWgPix < pend) issue(p0 + kWgPix);
 #pragma unroll
     for (int kk = 0; kk < kWgPix; kk += 32) {
       bf16x8 a[2], bb[2];

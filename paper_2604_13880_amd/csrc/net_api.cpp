@@ -130,6 +130,8 @@ int cg_net_create(cg_ctx* ctx, const cg_net_config* cfg, cg_net** out) {
       cfg->width > 8192)
     return fail(ctx, CG_EINVAL, "cg_net_create: height and width must be multiples of 2^(levels-1), <= 8192");
   if (cfg->max_batch < 1) return fail(ctx, CG_EINVAL, "cg_net_create: max_batch must be >= 1");
+  if ((int64_t)cfg->max_batch * cfg->height * cfg->width >= (int64_t)1 << 24)
+    return fail(ctx, CG_EINVAL, "cg_net_create: max_batch x height x width must stay below 2^24 pixels");
   if (!std::isfinite(cfg->out_scale)) return fail(ctx, CG_EINVAL, "cg_net_create: bad out_scale");
   if (cfg->in_channels < 1 || cfg->in_channels > 8) return fail(ctx, CG_EINVAL, "cg_net_create: in_channels must be 1..8");
   if (!std::isfinite(cfg->residual_gain) || (cfg->residual_gain != 0.f && cfg->in_channels < 3))

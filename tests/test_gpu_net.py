@@ -266,6 +266,8 @@ def test_net_argument_checks(ctx):
         Bd.Net(ctx, base_channels=16, levels=2, height=32, width=32)
     with pytest.raises(Bd.CartogramError):
         Bd.Net(ctx, base_channels=32, levels=3, height=30, width=32)
+    with pytest.raises(Bd.CartogramError):   # 2^24 pixels per batch
+        Bd.Net(ctx, base_channels=32, levels=2, height=1024, width=1024, max_batch=16)
     net = Bd.Net(ctx, base_channels=32, levels=2, height=32, width=32, max_batch=1)
     import torch
     with pytest.raises(Bd.CartogramError):
