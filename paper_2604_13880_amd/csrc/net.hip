@@ -338,9 +338,10 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
     for (int f = 0; f < 2; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
   // Per step of kWgPix pixels: the g tile (pixels x 32 channels, one chunk
   // of 8 channels per thread) and the patch tile (pixels x 128 columns of
-  // K, four chunks of 8 columns per thread, C_in % 8 == 0) are loaded from
-  // clamped addresses, the next step's while this one's products run, and
-  // written to LDS transposed so that pixels are the reduction axis.
+  // K, 8 columns of four consecutive pixels per thread, C_in % 8 == 0) are
+  // loaded from clamped addresses, the next step's while this one's
+  // products run, and written to LDS transposed so that pixels are the
+  // reduction axis.
   constexpr int NB = kWgPix * 16 / 256;
   u16x8 gv, bv[NB];
   bool gok, bok[NB];
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int p = (int)p0 + (t >> 4) + 16 * i;
+      const int p = (int)p0 + NB * (t >> 4) + i;   // NB consecutive pixels per thread
       int b, rem, y, x;
       divmod24(p, HWi, inv_hw, b, rem);
       divmod24(rem, W, inv_w, y, x);
@@ -379,12 +380,14 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict_
 #pragma unroll
         for (int e = 0; e < 8; ++e) As[cc + e][pi] = gok ? gv[e] : (uint16_t)0;
       }
+      // this thread's NB pixels are consecutive: one 8-byte store per column
+      static_assert(NB == 4, "four pixels per 8-byte store");
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const int c = t + 256 * i;
-        const int pi = c >> 4, kk = (c & 15) * 8;
+      for (int e = 0; e < 8; ++e) {
+        u16x4 w;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[kk + e][pi] = bok[i] ? bv[i][e] : (uint16_t)0;
+        for (int i = 0; i < NB; ++i) w[i] = bok[i] ? bv[i][e] : (uint16_t)0;
+        *(u16x4*)&Bs[kk_t + e][NB * (t >> 4)] = w;
       }
     } else {
       // g tile as above; patch element by element (any C_in)
