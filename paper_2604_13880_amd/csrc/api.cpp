@@ -27,7 +27,7 @@
 
 namespace cgk {
 void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
-                   void* u);
+                   void* u, bool rule = false);
 bool launch_sat(const Batch& B, int prec, int tw, int th, bool dense, bool il, int64_t tiles, int64_t c1,
                 int64_t c2, hipStream_t s, StageHook h, void* u);
 bool sat_shape_supported(int tw, int th);
@@ -311,9 +311,12 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     const Inst& I = P.inst[k];
     SatLayout L = cgk::sat_layout(I.N, tw, th);
     // every instance gets an edge block: its first one clears the totals
-    // the rasteriser's fill accumulates
+    // the rasteriser's fill accumulates; with single-edge blocks that is
+    // a block of its own (which also runs the previous iteration's
+    // stopping rule inside the iteration loop)
     const int64_t cnt[8] = {
-        std::max<int64_t>(1, (I.n_edges + edges_per_block - 1) / edges_per_block),
+        P.emit_ept == 1 ? (I.n_edges + edges_per_block - 1) / edges_per_block + 1
+                        : std::max<int64_t>(1, (I.n_edges + edges_per_block - 1) / edges_per_block),
         (I.N + kFillRows - 1) / kFillRows,
         (int64_t)L.ntx * L.nty,
         (L.NY + L.nty + 1 + 255) / 256,
@@ -474,7 +477,12 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   cgk::StageHook h = prof ? prof_hook : nullptr;
   void* u = prof ? (void*)&hc : nullptr;
   auto hk = [&](int s, int after) { if (h) h(s, after, u); };
-  cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, h, u);
+  // with single-edge emit blocks the stopping rule of the previous
+  // iteration runs in the emit pass's totals blocks, and the last
+  // iteration's follows the loop (launch_rule); else each iteration ends
+  // with its own
+  const bool fold = P.emit_ept == 1;
+  cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, h, u, fold && it > 0);
   const bool fuse = P.fuse_lut;
   cgk::Batch Bl = P.B;
   if (fuse) {
@@ -491,9 +499,23 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   hk(cgk::ST_AREAS, 0);
   cgk::launch_areas(P.B, P.reg_blocks, st);
   hk(cgk::ST_AREAS, 1);
-  hk(cgk::ST_ERR, 0);
+  if (!fold) {
+    hk(cgk::ST_ERR, 0);
+    cgk::launch_err(P.B, 0, st);
+    hk(cgk::ST_ERR, 1);
+  }
+}
+
+// The stopping rule after the last of a run of iterations whose earlier
+// ones ran in the next iteration's emit pass.  Timed in the first
+// iteration's event slots (the stage has no other launch to time).
+void launch_rule(const Plan& P, hipStream_t st, cg_ctx* c) {
+  if (P.emit_ept != 1) return;   // each iteration ended with its own
+  HookCtx hc{c, 0};
+  const bool prof = c && c->prof_stage >= 0;
+  if (prof) prof_hook(cgk::ST_ERR, 0, &hc);
   cgk::launch_err(P.B, 0, st);
-  hk(cgk::ST_ERR, 1);
+  if (prof) prof_hook(cgk::ST_ERR, 1, &hc);
 }
 
 int check_launch(cg_ctx* c) {
@@ -1152,6 +1174,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     if (!exec) {
       HIP_OK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
       for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
+      launch_rule(P, st, c);
       HIP_OK(c, hipStreamEndCapture(st, &graph));
       HIP_OK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
       if (!prof) {
@@ -1207,6 +1230,7 @@ int run_batch(cg_ctx* c, const std::vector<Spec>& specs, const std::vector<StepR
     }
     if (eager) {
       for (int it = 0; it < K; ++it) launch_iteration(P, st, c, it);
+      launch_rule(P, st, c);
       if ((rc = check_launch(c))) break;
     } else if (hipGraphLaunch(exec, st) != hipSuccess) {
       rc = fail(c, CG_EDEVICE, "cg_step_series: graph launch failed");

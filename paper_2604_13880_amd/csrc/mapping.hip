@@ -5,28 +5,6 @@
 
 namespace cgk {
 
-// Fixed-order block reductions over 256 threads (deterministic): a
-// butterfly of lane exchanges within each wavefront (lane 0's total is the
-// one used), then the four wavefront totals in a fixed order.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return r;
-}
-__device__ __forceinline__ double block_max(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  __syncthreads();
-  return r;
-}
-
 // Step 3: density LUT.  d0 = sum s / sum o over map regions with o > 0,
 // background density b*d0 (or from a prescribed background mass); the LUT is scaled so the texture mass is N^2
 // (the map is invariant to a common scale of the density).
@@ -340,96 +318,7 @@ __global__ __launch_bounds__(256) void k_err(Batch B, int mode, float alpha) {
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
   __shared__ double red[256];
-  const int t = threadIdx.x, R = I.R;
-  g_ptr<IterState> st = I.st;
-  // the state the stopping rule reads (written by this kernel alone), loaded
-  // while the sums run
-  int32_t st_eval = 0, st_iter = 0, st_bestk = 0, st_flags = 0;
-  double st_best = 0.0;
-  if (t == 0 && mode == 0) {
-    st_eval = st->evaluated;
-    st_iter = st->iter;
-    st_bestk = st->best_k;
-    st_flags = st->flags;
-    st_best = st->best_xi;
-  }
-  double sa = 0.0, ss = 0.0, bad = 0.0;
-  double A1 = 0.0;   // the thread's first region, kept for the second pass
-  float s1 = 0.f;
-  for (int v = 1 + t; v <= R; v += 256) {
-    const float s = I.values[v - 1];
-    const double A = I.areas[v];
-    if (v == 1 + t) {
-      A1 = A;
-      s1 = s;
-    }
-    sa += A;
-    ss += (double)s;
-    bad = (s >= 0.f && s <= 3.4028235e38f) ? bad : 1.0;   // NaN, infinite or negative value
-  }
-  sa = block_sum(sa, red);
-  ss = block_sum(ss, red);
-  bad = block_max(bad, red);
-  double se = 0.0, me = 0.0;
-  for (int v = 1 + t; v <= R; v += 256) {
-    const double A = v == 1 + t ? A1 : I.areas[v];
-    const double w = (double)(v == 1 + t ? s1 : I.values[v - 1]) * sa / ss;
-    const double m = fmax(A, w);
-    const double e = m > 0.0 ? fabs(A - w) / m : 0.0;
-    se += e;
-    me = fmax(me, e);
-  }
-  se = block_sum(se, red);
-  me = block_max(me, red);
-  if (t != 0) return;
-  const double xi = me, eps = R > 0 ? se / R : 0.0;
-  I.areas[0] = 1.0 - sa;
-  st->xi = xi;
-  st->eps = eps;
-  if (mode == 2) {
-    st->xi0 = xi;
-    st->ws_best = xi;
-    st->ws_alpha = 0.f;
-  }
-  if (mode == 3 && I.init_field != nullptr) {
-    // a trial step of the warm start: kept if the moved map did not fold
-    // (no contested pixel, no overflowing crossing buffer) and its error is
-    // the lowest so far, below the plain start's
-    const int f = st->flags;
-    if (!(f & CG_FLAG_OVERFLOW) && st->contested == 0 && xi < st->ws_best) {
-      st->ws_best = xi;
-      st->ws_alpha = alpha;
-    }
-    st->flags = f & ~CG_FLAG_OVERFLOW;
-  }
-  if (mode == 4 && I.init_field != nullptr && st->ws_alpha == 0.f) st->flags |= CG_FLAG_FALLBACK;
-  if (mode != 0) return;
-  int it, best_k = st_bestk;
-  if (!st_eval) {
-    st->evaluated = 1;
-    it = 0;
-    st->best_xi = xi;
-    st->best_k = best_k = 0;
-  } else {
-    it = st_iter + 1;
-    st->iter = it;
-    if (xi < st_best) {
-      st->best_xi = xi;
-      st->best_k = best_k = it;
-    }
-  }
-  int done = 0, status = CG_STATUS_MAXITER;
-  if (bad > 0.0 || !(ss > 0.0)) {   // the values define no density: nothing is iterated
-    st->flags = st_flags | CG_FLAG_BADVALUES;
-    done = 1;
-    status = CG_STATUS_ERROR;
-  } else if (st_flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }
-  else if (I.fixed_iters > 0) { done = it >= I.fixed_iters; status = CG_STATUS_MAXITER; }
-  else if (xi < (double)I.tol) { done = 1; status = CG_STATUS_CONVERGED; }
-  else if (it - best_k >= I.patience) { done = 1; status = CG_STATUS_STALLED; }
-  else if (it >= I.max_iters) { done = 1; status = CG_STATUS_MAXITER; }
-  st->status = status;
-  st->done = done;
+  (void)stopping_rule(I, mode, alpha, red);
 }
 
 // Reset the iteration state and copy the starting positions.

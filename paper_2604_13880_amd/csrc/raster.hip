@@ -16,7 +16,9 @@
 //   k_raster_emit   one thread per edge: (p0, region A, region B) records
 //                   appended to the bucket of every row the edge crosses
 //                   (kFillXing records per row; an integer atomic per
-//                   crossing picks the slot)
+//                   crossing picks the slot); one more block per instance
+//                   clears the fill's totals after the previous
+//                   iteration's stopping rule
 //   k_raster_fill   one wavefront per row: rank sort by p0, claim sets by
 //                   lane scans, write labels, per-region counts aggregated
 //                   in LDS
@@ -35,18 +37,42 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
 
 // One thread per EPT edges (e0 + 256 j): all their loads are issued before
 // any is used, which shortens the chain of dependent loads per edge when a
-// launch has many rounds of blocks.
-template <int EPT>
+// launch has many rounds of blocks.  TOT = 0: the instance's first block
+// also clears the totals the fill accumulates.  TOT = 1, 2 (launches of
+// single-edge blocks): every instance has one block more than its edges
+// need, its first, the totals block, which clears them, with TOT = 2 after
+// running the previous iteration's stopping rule (Step 7; the areas are
+// complete, the next launch is the fill), so the iteration needs no launch
+// of its own for it.  When the rule ends the instance, the totals stay as
+// they are; the crossings that the other blocks may still append belong
+// to no fill (the fill and every later kernel skip the instance, and the
+// next call starts from cleared buckets).
+template <int EPT, int TOT>
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_edges, KD_EDGES, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
-  if (blockIdx.x == first) {   // the instance's first block: clear the fill's totals
+  int64_t bi = blockIdx.x - first;
+  if (TOT == 0 && bi == 0) {
     for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
     if (threadIdx.x == 0) I.st->contested = 0;
   }
-  const int64_t e0 = (int64_t)(blockIdx.x - first) * (256 * EPT) + threadIdx.x;
+  if (TOT != 0 && bi == 0) {   // the totals block
+    if (TOT == 2) {
+      __shared__ double red[256];
+      __shared__ int done_s;
+      const int done = stopping_rule(I, 0, 0.f, red);
+      if (threadIdx.x == 0) done_s = done;
+      __syncthreads();
+      if (done_s) return;
+    }
+    for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
+    if (threadIdx.x == 0) I.st->contested = 0;
+    return;
+  }
+  if (TOT != 0) --bi;
+  const int64_t e0 = bi * (256 * EPT) + threadIdx.x;
   if (e0 >= I.n_edges) return;
   const int N = I.N;
   const float scale = (float)(kSub * N);
@@ -693,12 +719,20 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
 }
 
 void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
-                   void* u) {
+                   void* u, bool rule) {
   auto hk = [&](int st, int after) { if (h) h(st, after, u); };
   if (edge_blocks > 0) {
     hk(ST_RASTER_EMIT, 0);
-    if (ept == kEmitEdges) hipLaunchKernelGGL(k_raster_emit<kEmitEdges>, dim3(edge_blocks), dim3(256), 0, s, B);
-    else hipLaunchKernelGGL(k_raster_emit<1>, dim3(edge_blocks), dim3(256), 0, s, B);
+    // totals blocks (and the rule in them) only in launches of single-edge
+    // blocks (few blocks, where a launch of its own costs most); with four
+    // edges per thread the extra block per instance made the 64 x 2048^2
+    // emit 9% slower
+    if (ept == kEmitEdges)
+      hipLaunchKernelGGL((k_raster_emit<kEmitEdges, 0>), dim3(edge_blocks), dim3(256), 0, s, B);
+    else if (rule)
+      hipLaunchKernelGGL((k_raster_emit<1, 2>), dim3(edge_blocks), dim3(256), 0, s, B);
+    else
+      hipLaunchKernelGGL((k_raster_emit<1, 1>), dim3(edge_blocks), dim3(256), 0, s, B);
     hk(ST_RASTER_EMIT, 1);
   }
   hk(ST_RASTER_FILL, 0);
