@@ -18,26 +18,37 @@ __global__ __launch_bounds__(256) void k_density(Batch B) {
   auto count = [&](int v) -> double { return (double)I.counts[v]; };
   const double NN = (double)I.N * (double)I.N;
   const bool poly = I.area_source == CG_AREA_POLYGON;
-  double ss = 0.0, so = 0.0;
+  const double c0 = count(0);
+  // one pass over the regions (every load of a region issued before any
+  // is used; the thread's first region kept for the table): sum s, sum o
+  // and sum s / o * count, whose total does not depend on d0
+  double ss = 0.0, so = 0.0, cm = 0.0, q1 = 0.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : count(v);
-    if (o > 0.0) ss += (double)I.values[v - 1];
+    const double cnt = count(v);
+    const double ar = I.areas[v];
+    const double sv = (double)I.values[v - 1];
+    const double o = poly ? ar * NN : cnt;
+    const double q = o > 0.0 ? sv / o : 0.0;
+    if (v == 1 + t) q1 = q;
+    if (o > 0.0) {
+      ss += sv;
+      cm += q * cnt;
+    }
     so += o;
   }
   ss = block_sum(ss, red);
   so = block_sum(so, red);
   const double d0 = so > 0.0 ? ss / so : 1.0;
-  const double bdv = background_density(I, d0, count(0));
-  double cm = 0.0;
-  for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : count(v);
-    if (o > 0.0) cm += (double)I.values[v - 1] / o * count(v);
-  }
-  cm = block_sum(cm, red) + bdv * count(0);
+  const double bdv = background_density(I, d0, c0);
+  cm = block_sum(cm, red) + bdv * c0;
   const double kappa = cm > 0.0 ? NN / cm : 1.0;
   for (int v = 1 + t; v <= R; v += 256) {
-    const double o = poly ? I.areas[v] * NN : count(v);
-    I.lut[v] = o > 0.0 ? (float)(kappa * ((double)I.values[v - 1] / o)) : 0.f;
+    double q = q1;
+    if (v != 1 + t) {
+      const double o = poly ? I.areas[v] * NN : count(v);
+      q = o > 0.0 ? (double)I.values[v - 1] / o : 0.0;
+    }
+    I.lut[v] = (float)(kappa * q);
   }
   for (int v = R + 1 + t; v < I.n_lut; v += 256) I.lut[v] = 0.f;
   if (t == 0) {
@@ -291,7 +302,7 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
   for (int e0 = I.reg_pair_off[v - 1] + t; e0 < end; e0 += 256 * U) {
     i2 pr[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) pr[u] = e0 + 256 * u < end ? *(g_ptr<const i2>)(I.reg_pairs + e0 + 256 * u) : i2{0, 0};
+    for (int u = 0; u < U; ++u) pr[u] = *(g_ptr<const i2>)(I.reg_pairs + min(e0 + 256 * u, end - 1));   // unconditional
     float2 a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {

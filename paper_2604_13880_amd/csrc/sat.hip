@@ -260,14 +260,22 @@ __device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool p
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, R = I.R;
   const double NN = (double)I.N * (double)I.N;
   const bool poly = I.area_source == CG_AREA_POLYGON;
+  const double c0 = (double)I.counts[0];   // background pixels, needed after the sums
   double ss = 0.0, so = 0.0, sc = 0.0;
+  // the thread's first region is kept for the table (most instances have
+  // at most one region per thread); every load of a region is issued
+  // before any is used
+  double q1 = 0.0;
   for (int v = 1 + t; v <= R; v += NT) {
     const double cnt = (double)I.counts[v];
-    const double o = poly ? I.areas[v] * NN : cnt;
+    const double ar = I.areas[v];
+    const double s = (double)I.values[v - 1];
+    const double o = poly ? ar * NN : cnt;
+    const double q = o > 0.0 ? s / o : 0.0;
+    if (v == 1 + t) q1 = q;
     if (o > 0.0) {
-      const double s = (double)I.values[v - 1];
       ss += s;
-      sc += s / o * cnt;
+      sc += q * cnt;
     }
     so += o;
   }
@@ -288,13 +296,17 @@ __device__ __forceinline__ void density_lut(const InstG& I, float* lut_s, bool p
     sc += part[2][i];
   }
   const double d0 = so > 0.0 ? ss / so : 1.0;
-  const double bdv = background_density(I, d0, (double)I.counts[0]);
-  const double cm = sc + bdv * (double)I.counts[0];
+  const double bdv = background_density(I, d0, c0);
+  const double cm = sc + bdv * c0;
   const double kappa = cm > 0.0 ? NN / cm : 1.0;
   g_ptr<float> lut = (g_ptr<float>)I.lut;
   for (int v = 1 + t; v <= R; v += NT) {
-    const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
-    const float x = o > 0.0 ? (float)(kappa * ((double)I.values[v - 1] / o)) : 0.f;
+    double q = q1;
+    if (v != 1 + t) {
+      const double o = poly ? I.areas[v] * NN : (double)I.counts[v];
+      q = o > 0.0 ? (double)I.values[v - 1] / o : 0.0;
+    }
+    const float x = (float)(kappa * q);
     lut_s[v] = x;
     if (publish) lut[v] = x;
   }
