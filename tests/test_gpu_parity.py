@@ -342,6 +342,35 @@ def test_stopping_rule_matches_oracle(ctx):
         assert r["status"][0] == status == o.status and r["iters"][0] == o.iters
 
 
+def test_stopping_rule_same_for_every_graph_length(ctx):
+    """For launches of single-edge emit blocks the stopping rule of an
+    iteration runs in the next iteration's emit pass, and in a launch of
+    its own after the last iteration of each graph.  The decision must not
+    depend on where a graph ends: graphs of 32, 5 and 1 iterations and
+    eager launches give the same iteration count, status, errors and
+    positions, bit for bit, whether the run ends by the tolerance, the cap,
+    a stall, fixed_iters or already at the start."""
+    m = voronoi_map(1003, 24, 3000, fractal=True)
+    s = lognormal_values(1003, 24, 0.8).astype(np.float32)
+    N = 256
+    gm = ctx.map_from(m)
+    cases = [dict(), dict(max_iters=13), dict(patience=2), dict(fixed_iters=7), dict(fixed_iters=33),
+             dict(tol=1.0)]
+    for kw in cases:
+        runs = []
+        for gi in (32, 5, 1, -3):
+            r = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, precision=1, **kw)], graph_iters=gi)[0]
+            runs.append((int(r["iters"][0]), int(r["status"][0]), float(r["xi"][0]), float(r["eps"][0]),
+                         _np(r["xy"])[0].copy()))
+        say("rule", kw, [(a, b, c) for a, b, c, _, _ in runs])
+        for other in runs[1:]:
+            assert other[:4] == runs[0][:4], (kw, other[:4], runs[0][:4])
+            assert np.array_equal(other[4], runs[0][4]), kw
+    o = oc.run(m, s.astype(np.float64), N, state_dtype=np.float32, max_iters=13)
+    r = ctx.step_series([dict(map=gm, xy0=m.xy32(), N=N, values=s, precision=1, max_iters=13)], graph_iters=5)[0]
+    assert int(r["iters"][0]) == o.iters and int(r["status"][0]) == o.status
+
+
 def test_polygon_area_source_iteration(ctx):
     m = voronoi_map(1004, 20, 1200, fractal=True)
     s = lognormal_values(1004, 20, 1.0).astype(np.float32)
