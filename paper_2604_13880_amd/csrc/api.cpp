@@ -312,12 +312,14 @@ int build_plan(cg_ctx* c, const std::vector<Spec>& specs, int prec, int tw, int 
     SatLayout L = cgk::sat_layout(I.N, tw, th);
     // every instance gets an edge block: its first one clears the totals
     // the rasteriser's fill accumulates; with single-edge blocks that is
-    // a block of its own (which also runs the previous iteration's
-    // stopping rule inside the iteration loop)
+    // a block of its own, followed by one block per region (the previous
+    // iteration's areas, inside the iteration loop), and the fill has a
+    // block more (that iteration's stopping rule)
+    const bool one = P.emit_ept == 1;
     const int64_t cnt[8] = {
-        P.emit_ept == 1 ? (I.n_edges + edges_per_block - 1) / edges_per_block + 1
-                        : std::max<int64_t>(1, (I.n_edges + edges_per_block - 1) / edges_per_block),
-        (I.N + kFillRows - 1) / kFillRows,
+        one ? (I.n_edges + edges_per_block - 1) / edges_per_block + 1 + I.R
+            : std::max<int64_t>(1, (I.n_edges + edges_per_block - 1) / edges_per_block),
+        (I.N + kFillRows - 1) / kFillRows + (one ? 1 : 0),
         (int64_t)L.ntx * L.nty,
         (L.NY + L.nty + 1 + 255) / 256,
         (L.NX + 1 + (int64_t)L.LA + L.LB + (256 / L.carry_ch) - 1) / (256 / L.carry_ch),
@@ -477,10 +479,10 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   cgk::StageHook h = prof ? prof_hook : nullptr;
   void* u = prof ? (void*)&hc : nullptr;
   auto hk = [&](int s, int after) { if (h) h(s, after, u); };
-  // with single-edge emit blocks the stopping rule of the previous
-  // iteration runs in the emit pass's totals blocks, and the last
-  // iteration's follows the loop (launch_rule); else each iteration ends
-  // with its own
+  // with single-edge emit blocks the previous iteration's areas are
+  // computed in the emit pass and its stopping rule runs in the fill, and
+  // the last iteration's follow the loop (launch_rule); else each
+  // iteration ends with its own
   const bool fold = P.emit_ept == 1;
   cgk::launch_raster(P.B, P.emit_ept, P.edge_blocks, P.row_blocks, st, h, u, fold && it > 0);
   const bool fuse = P.fuse_lut;
@@ -496,23 +498,27 @@ void launch_iteration(const Plan& P, hipStream_t st, cg_ctx* c, int it) {
   hk(cgk::ST_MAP, 0);
   cgk::launch_map(P.B, P.prec, P.il, P.pt_blocks, st);
   hk(cgk::ST_MAP, 1);
-  hk(cgk::ST_AREAS, 0);
-  cgk::launch_areas(P.B, P.reg_blocks, st);
-  hk(cgk::ST_AREAS, 1);
   if (!fold) {
+    hk(cgk::ST_AREAS, 0);
+    cgk::launch_areas(P.B, P.reg_blocks, st);
+    hk(cgk::ST_AREAS, 1);
     hk(cgk::ST_ERR, 0);
     cgk::launch_err(P.B, 0, st);
     hk(cgk::ST_ERR, 1);
   }
 }
 
-// The stopping rule after the last of a run of iterations whose earlier
-// ones ran in the next iteration's emit pass.  Timed in the first
-// iteration's event slots (the stage has no other launch to time).
+// The areas and the stopping rule after the last of a run of iterations
+// whose earlier ones ran in the next iteration's emit pass and fill.
+// Timed in the first iteration's event slots (the stages have no other
+// launches to time).
 void launch_rule(const Plan& P, hipStream_t st, cg_ctx* c) {
   if (P.emit_ept != 1) return;   // each iteration ended with its own
   HookCtx hc{c, 0};
   const bool prof = c && c->prof_stage >= 0;
+  if (prof) prof_hook(cgk::ST_AREAS, 0, &hc);
+  cgk::launch_areas(P.B, P.reg_blocks, st);
+  if (prof) prof_hook(cgk::ST_AREAS, 1, &hc);
   if (prof) prof_hook(cgk::ST_ERR, 0, &hc);
   cgk::launch_err(P.B, 0, st);
   if (prof) prof_hook(cgk::ST_ERR, 1, &hc);

@@ -44,7 +44,7 @@ struct IterState {
   double xi0;         // max error of the plain (not warm-started) start
   double ws_best;     // lowest max error among the warm start's trial steps
   float ws_alpha;     // chosen warm-start step (0: plain start)
-  int32_t pad1;
+  int32_t flags_rule; // flags as the emit pass found them (read by the rule run inside the fill)
 };
 
 // Pointer policies of the instance descriptor: the host fills generic
@@ -222,6 +222,34 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// Region v's area (Step 7: FP64 shoelace over its rings' vertex pairs in
+// ring order), by one block of 256 threads; thread 0 stores it.
+__device__ __forceinline__ void region_area(const InstG& I, int v, double* red) {
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  const int end = I.reg_pair_off[v];
+  // four of the thread's edges per round: their loads are all in flight
+  // before the first is used (the terms are added in the same order)
+  constexpr int U = 4;
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  for (int e0 = I.reg_pair_off[v - 1] + t; e0 < end; e0 += 256 * U) {
+    i2 pr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pr[u] = *(g_ptr<const i2>)(I.reg_pairs + min(e0 + 256 * u, end - 1));   // unconditional
+    float2 a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = ld2(I.xy + pr[u].x);
+      b[u] = ld2(I.xy + pr[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + 256 * u < end) acc += (double)a[u].x * (double)b[u].y - (double)b[u].x * (double)a[u].y;
+  }
+  acc = block_sum(acc, red);
+  if (t == 0) I.areas[v] = 0.5 * acc;
+}
+
 // Step 7 for one instance, by one block of 256 threads: region weights
 // w(v) = s(v) O / sum s, the mean and max area errors eps and xi, and in
 // mode 0 the stopping rule (max error below tol, no new minimum within
@@ -229,7 +257,8 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // the instance's state by thread 0; modes 2-4 score the warm start's
 // trial steps.  Returns the stopping decision of mode 0 in thread 0 (0 in
 // the other threads).
-__device__ __forceinline__ int stopping_rule(const InstG& I, int mode, float alpha, double* red) {
+__device__ __forceinline__ int stopping_rule(const InstG& I, int mode, float alpha, double* red,
+                                             bool flags_snapshot = false) {
   const int t = threadIdx.x, R = I.R;
   g_ptr<IterState> st = I.st;
   // the state the stopping rule reads (written only by the one block that
@@ -240,7 +269,7 @@ __device__ __forceinline__ int stopping_rule(const InstG& I, int mode, float alp
     st_eval = st->evaluated;
     st_iter = st->iter;
     st_bestk = st->best_k;
-    st_flags = st->flags;
+    st_flags = flags_snapshot ? st->flags_rule : st->flags;
     st_best = st->best_xi;
   }
   double sa = 0.0, ss = 0.0, bad = 0.0;
@@ -310,7 +339,7 @@ __device__ __forceinline__ int stopping_rule(const InstG& I, int mode, float alp
   }
   int done = 0, status = CG_STATUS_MAXITER;
   if (bad > 0.0 || !(ss > 0.0)) {   // the values define no density: nothing is iterated
-    st->flags = st_flags | CG_FLAG_BADVALUES;
+    g_atomic_or(&st->flags, (int32_t)CG_FLAG_BADVALUES);   // other blocks may set flags meanwhile
     done = 1;
     status = CG_STATUS_ERROR;
   } else if (st_flags & CG_FLAG_OVERFLOW) { done = 1; status = CG_STATUS_ERROR; }

@@ -291,30 +291,7 @@ __global__ __launch_bounds__(256) void k_areas(Batch B) {
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
   __shared__ double red[256];
-  const int v = 1 + (int)(blockIdx.x - first);
-  const int t = threadIdx.x;
-  double acc = 0.0;
-  const int end = I.reg_pair_off[v];
-  // four of the thread's edges per round: their loads are all in flight
-  // before the first is used (the terms are added in the same order)
-  constexpr int U = 4;
-  typedef int i2 __attribute__((ext_vector_type(2)));
-  for (int e0 = I.reg_pair_off[v - 1] + t; e0 < end; e0 += 256 * U) {
-    i2 pr[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) pr[u] = *(g_ptr<const i2>)(I.reg_pairs + min(e0 + 256 * u, end - 1));   // unconditional
-    float2 a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      a[u] = ld2(I.xy + pr[u].x);
-      b[u] = ld2(I.xy + pr[u].y);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e0 + 256 * u < end) acc += (double)a[u].x * (double)b[u].y - (double)b[u].x * (double)a[u].y;
-  }
-  acc = block_sum(acc, red);
-  if (t == 0) I.areas[v] = 0.5 * acc;
+  region_area(I, 1 + (int)(blockIdx.x - first), red);
 }
 
 // Cartographic errors and the stopping rule (Method, end of the static

@@ -39,14 +39,13 @@ __device__ __forceinline__ void crossed_rows(int ya, int yb, int N, int& q0, int
 // any is used, which shortens the chain of dependent loads per edge when a
 // launch has many rounds of blocks.  TOT = 0: the instance's first block
 // also clears the totals the fill accumulates.  TOT = 1, 2 (launches of
-// single-edge blocks): every instance has one block more than its edges
-// need, its first, the totals block, which clears them, with TOT = 2 after
-// running the previous iteration's stopping rule (Step 7; the areas are
-// complete, the next launch is the fill), so the iteration needs no launch
-// of its own for it.  When the rule ends the instance, the totals stay as
-// they are; the crossings that the other blocks may still append belong
-// to no fill (the fill and every later kernel skip the instance, and the
-// next call starts from cleared buckets).
+// single-edge blocks): every instance has R + 1 blocks more than its edges
+// need: first the totals block, which clears the totals, then one block
+// per region, which with TOT = 2 computes the region's area from the
+// positions the previous iteration's mapping left (Step 7; the stopping
+// rule of that iteration then runs inside the fill, and the iteration
+// needs no launch of its own for either).  The totals block also records
+// the flags as they are before the fill, which is what that rule reads.
 template <int EPT, int TOT>
 __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
   int64_t first;
@@ -58,20 +57,24 @@ __global__ __launch_bounds__(256) void k_raster_emit(Batch B) {
     for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
     if (threadIdx.x == 0) I.st->contested = 0;
   }
-  if (TOT != 0 && bi == 0) {   // the totals block
-    if (TOT == 2) {
-      __shared__ double red[256];
-      __shared__ int done_s;
-      const int done = stopping_rule(I, 0, 0.f, red);
-      if (threadIdx.x == 0) done_s = done;
-      __syncthreads();
-      if (done_s) return;
+  if (TOT != 0) {
+    if (bi == 0) {   // the totals block
+      for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
+      if (threadIdx.x == 0) {
+        I.st->contested = 0;
+        if (TOT == 2) I.st->flags_rule = I.st->flags;
+      }
+      return;
     }
-    for (int v = threadIdx.x; v <= I.R; v += 256) I.counts[v] = 0;
-    if (threadIdx.x == 0) I.st->contested = 0;
-    return;
+    if (bi <= I.R) {   // region bi's area
+      if (TOT == 2) {
+        __shared__ double red[256];
+        region_area(I, (int)bi, red);
+      }
+      return;
+    }
+    bi -= 1 + I.R;
   }
-  if (TOT != 0) --bi;
   const int64_t e0 = bi * (256 * EPT) + threadIdx.x;
   if (e0 >= I.n_edges) return;
   const int N = I.N;
@@ -261,11 +264,27 @@ __device__ __forceinline__ uint32_t wave_add_scan(uint32_t x) {
 // crossing k is the parity of the crossings <= k with that region on one
 // side only (a ballot and a popcount).  The serial walk of the claim set
 // remains for long rows of maps with more regions than the bitmap holds.
+//
+// LEAD (launches of single-edge emit blocks): every instance has one block
+// more, its first, which with RULE runs the stopping rule of the previous
+// iteration (the emit pass before has computed that iteration's areas and
+// recorded the flags as they were before this fill, which the rule reads
+// instead of the flags the other blocks are setting).  The rows of an
+// instance the rule ends are still filled in this launch; no kernel after
+// it reads them, and the run's positions are final.
+template <bool LEAD, bool RULE>
 __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   int64_t first;
   const int k = find_inst(B, B.off_rows, KD_ROWS, blockIdx.x, first);
   const InstG I = inst_of(B, k);  // register copy: stores below cannot alias it
   if (inst_done(B, k)) return;
+  if (LEAD && blockIdx.x == first) {
+    if (RULE) {
+      __shared__ double red[256];
+      (void)stopping_rule(I, 0, 0.f, red, true);
+    }
+    return;
+  }
   constexpr int RPW = kFillRows / 4;   // rows per wavefront
   __shared__ uint64_t xs[4][kFillXing];
   uint64_t (*const srt)[kFillXing] = xs;   // sorted in place: every lane holds its records before any is written
@@ -276,7 +295,7 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
   __shared__ unsigned long long contested_blk;
   const int N = I.N, R = I.R;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int q0 = (int)(blockIdx.x - first) * kFillRows;
+  const int q0 = (int)(blockIdx.x - first - (LEAD ? 1 : 0)) * kFillRows;
   const bool lds_counts = (R + 1) <= kLutLds;
   // the first row's crossing count and its bucket's first 64 slots are
   // read together (the slots exist whatever the count)
@@ -721,13 +740,14 @@ __global__ __launch_bounds__(256) void k_raster_fill(Batch B) {
 void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blocks, hipStream_t s, StageHook h,
                    void* u, bool rule) {
   auto hk = [&](int st, int after) { if (h) h(st, after, u); };
+  // with single-edge blocks (few blocks, where a launch of its own costs
+  // most) the plan gives every instance its totals, area and rule blocks;
+  // with four edges per thread the extra blocks per instance made the
+  // 64 x 2048^2 emit 9% slower, so those plans have none
+  const bool one = ept != kEmitEdges;
   if (edge_blocks > 0) {
     hk(ST_RASTER_EMIT, 0);
-    // totals blocks (and the rule in them) only in launches of single-edge
-    // blocks (few blocks, where a launch of its own costs most); with four
-    // edges per thread the extra block per instance made the 64 x 2048^2
-    // emit 9% slower
-    if (ept == kEmitEdges)
+    if (!one)
       hipLaunchKernelGGL((k_raster_emit<kEmitEdges, 0>), dim3(edge_blocks), dim3(256), 0, s, B);
     else if (rule)
       hipLaunchKernelGGL((k_raster_emit<1, 2>), dim3(edge_blocks), dim3(256), 0, s, B);
@@ -736,7 +756,9 @@ void launch_raster(const Batch& B, int ept, int64_t edge_blocks, int64_t row_blo
     hk(ST_RASTER_EMIT, 1);
   }
   hk(ST_RASTER_FILL, 0);
-  hipLaunchKernelGGL(k_raster_fill, dim3(row_blocks), dim3(256), 0, s, B);
+  if (!one) hipLaunchKernelGGL((k_raster_fill<false, false>), dim3(row_blocks), dim3(256), 0, s, B);
+  else if (rule) hipLaunchKernelGGL((k_raster_fill<true, true>), dim3(row_blocks), dim3(256), 0, s, B);
+  else hipLaunchKernelGGL((k_raster_fill<true, false>), dim3(row_blocks), dim3(256), 0, s, B);
   hk(ST_RASTER_FILL, 1);
 }
 
