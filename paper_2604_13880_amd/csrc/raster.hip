@@ -16,12 +16,13 @@
 //   k_raster_emit   one thread per edge: (p0, region A, region B) records
 //                   appended to the bucket of every row the edge crosses
 //                   (kFillXing records per row; an integer atomic per
-//                   crossing picks the slot); one more block per instance
-//                   clears the fill's totals after the previous
-//                   iteration's stopping rule
+//                   crossing picks the slot); in launches of single-edge
+//                   blocks also a block that clears the fill's totals and
+//                   one block per region for the previous iteration's areas
 //   k_raster_fill   one wavefront per row: rank sort by p0, claim sets by
 //                   lane scans, write labels, per-region counts aggregated
-//                   in LDS
+//                   in LDS; in those launches also a block for the previous
+//                   iteration's stopping rule
 #include "cg_dev.h"
 
 namespace cgk {
