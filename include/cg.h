@@ -271,7 +271,9 @@ typedef struct {
   float* frames;    /* device [T-1][K-1][n_vertices][2] or NULL */
   int32_t* iters;   /* HOST [T] iterations done */
   int32_t* status;  /* HOST [T] CG_STATUS_* */
-  int32_t* flags;   /* HOST [T] CG_FLAG_* */
+  int32_t* flags;   /* HOST [T] CG_FLAG_*, over the run's rasterisations (in launches of up to 2M
+                       edges these include one of the final positions, made before the stopping
+                       rule ends the run; a flag from that one does not change the status) */
   double* eps;      /* HOST [T] final mean area error */
   double* xi;       /* HOST [T] final max area error */
   float* warm_step; /* HOST [T] warm-start step taken (0: plain start), or NULL */
