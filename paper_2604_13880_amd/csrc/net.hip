@@ -177,8 +177,12 @@ bool conv3_rows_ok(int Cin, int64_t P, int H, int W) {
   return Cin % 32 == 0 && W >= 16 && W <= 128 && (W & (W - 1)) == 0 && ((int64_t)H * W) % 256 == 0;
 }
 
+// With `deep` set, the input is the concatenation [nearest x2 upsampling
+// of deep (Cd channels at half resolution), in (Cin - Cd channels)] read in
+// place: a chunk of 32 channels comes from one of the two (Cd % 32 == 0).
 template <int MF, bool F32OUT>
 __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__ in, int Cin,
+                                                    const uint16_t* __restrict__ deep, int Cd,
                                                     const uint16_t* __restrict__ wA, const float* __restrict__ bias,
                                                     void* __restrict__ out, int Cout, int64_t P, int H, int W,
                                                     int relu) {
@@ -198,7 +202,9 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
   const int y0 = (int)((p0 - img * HW) / W);
   const int RB = 256 / W, Wp = W + 2;                   // rows of the block, padded row length
   const int npix = (RB + 2) * Wp;
-  const uint16_t* src0 = in + img * HW * Cin;
+  const int Cs = deep ? Cin - Cd : Cin, Coff = deep ? Cd : 0;   // channels of `in` and where they start
+  const uint16_t* src0 = in + img * HW * Cs;
+  const uint16_t* deep0 = deep ? deep + img * (HW / 4) * Cd : nullptr;
   // this lane's four pixels (local index wv*64 + 16f + lr): LDS pixel of tap (0, 0)
   int base[NF];
 #pragma unroll
@@ -231,8 +237,13 @@ __global__ __launch_bounds__(256) void k_conv3_rows(const uint16_t* __restrict__
       const int ty = pix / Wp, tx = pix - ty * Wp;
       const int yy = y0 - 1 + ty, xx = tx - 1;
       hok[i] = e < npix * 4 && yy >= 0 && yy < H && xx >= 0 && xx < W;
-      const int64_t off = hok[i] ? ((int64_t)yy * W + xx) * Cin + c0 + 8 * j : 0;
-      hv[i] = *(const u32x4*)(src0 + off);
+      if (deep0 && c0 < Cd) {   // uniform per chunk
+        const int64_t off = hok[i] ? ((int64_t)(yy >> 1) * (W >> 1) + (xx >> 1)) * Cd + c0 + 8 * j : 0;
+        hv[i] = *(const u32x4*)(deep0 + off);
+      } else {
+        const int64_t off = hok[i] ? ((int64_t)yy * W + xx) * Cs + (c0 - Coff) + 8 * j : 0;
+        hv[i] = *(const u32x4*)(src0 + off);
+      }
     }
 #pragma unroll
     for (int i = 0; i < A_IT; ++i) {
@@ -788,19 +799,21 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 bool conv3_supported(int Cin, int Cout) { return Cout % 32 == 0 && Cin >= 1; }
 
+// deep != nullptr (the concatenation read in place) only where
+// conv3_rows_ok holds and Cd % 32 == 0 (checked by the caller)
 template <bool F32OUT>
 static void conv3_t(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, void* out, int Cout, int Bn,
-                    int H, int W, int relu, hipStream_t s) {
+                    int H, int W, int relu, hipStream_t s, const uint16_t* deep = nullptr, int Cd = 0) {
   const int64_t P = (int64_t)Bn * H * W;
   const unsigned gx = (unsigned)((P + 255) / 256);
   const bool gen = Cin % 32 != 0;
   if (conv3_rows_ok(Cin, P, H, W)) {   // whole rows per block: P is a multiple of 256
     if (Cout % 64 == 0)
-      hipLaunchKernelGGL((k_conv3_rows<4, F32OUT>), dim3(gx, Cout / 64), dim3(256), 0, s, in, Cin, wA, bias, out, Cout,
-                         P, H, W, relu);
+      hipLaunchKernelGGL((k_conv3_rows<4, F32OUT>), dim3(gx, Cout / 64), dim3(256), 0, s, in, Cin, deep, Cd, wA, bias,
+                         out, Cout, P, H, W, relu);
     else
-      hipLaunchKernelGGL((k_conv3_rows<2, F32OUT>), dim3(gx, Cout / 32), dim3(256), 0, s, in, Cin, wA, bias, out, Cout,
-                         P, H, W, relu);
+      hipLaunchKernelGGL((k_conv3_rows<2, F32OUT>), dim3(gx, Cout / 32), dim3(256), 0, s, in, Cin, deep, Cd, wA, bias,
+                         out, Cout, P, H, W, relu);
     return;
   }
   if (Cout % 64 == 0) {
@@ -817,6 +830,14 @@ static void conv3_t(const uint16_t* in, int Cin, const uint16_t* wA, const float
 void launch_conv3(const uint16_t* in, int Cin, const uint16_t* wA, const float* bias, uint16_t* out, int Cout,
                   int Bn, int H, int W, int relu, hipStream_t s) {
   conv3_t<false>(in, Cin, wA, bias, out, Cout, Bn, H, W, relu, s);
+}
+// conv over [up(deep), skip] without the concatenation in memory; false
+// (nothing launched) where the row-staged convolution does not apply
+bool launch_conv3_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, const uint16_t* wA,
+                        const float* bias, uint16_t* out, int Cout, int Bn, int H, int W, int relu, hipStream_t s) {
+  if (Cd % 32 != 0 || !conv3_rows_ok(Cd + Cs, (int64_t)Bn * H * W, H, W)) return false;
+  conv3_t<false>(skip, Cd + Cs, wA, bias, out, Cout, Bn, H, W, relu, s, deep, Cd);
+  return true;
 }
 
 void launch_conv3_f32(const uint16_t* in, int Cin, const uint16_t* wA, float* out, int Cout, int Bn, int H, int W,

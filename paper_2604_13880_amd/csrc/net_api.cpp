@@ -30,6 +30,8 @@ void launch_relu_mask(const float* g, const uint16_t* act, uint16_t* gm, int64_t
 void launch_pool(const uint16_t* x, uint16_t* y, int Bn, int H, int W, int C, hipStream_t s);
 void launch_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, uint16_t* cat, int Bn, int H, int W,
                   hipStream_t s);
+bool launch_conv3_upcat(const uint16_t* deep, int Cd, const uint16_t* skip, int Cs, const uint16_t* wA,
+                        const float* bias, uint16_t* out, int Cout, int Bn, int H, int W, int relu, hipStream_t s);
 void launch_up_grad(const float* gcat, int Ccat, int Cd, float* gdeep, int Bn, int Ho, int Wo, hipStream_t s);
 void launch_skip_grad(const float* gcat, int Ccat, int Cd, const float* gpool, float* gskip, int Cs, int Bn,
                       int H, int W, hipStream_t s);
@@ -72,6 +74,8 @@ struct cg_net {
   uint16_t* x_in = nullptr;
   std::vector<uint16_t*> in_l, a_l, e_l;   // encoder: pooled input (l > 0), first and second conv outputs
   std::vector<uint16_t*> cat_l, da_l, d_l; // decoder (levels 0..L-2)
+  std::vector<char> cat_ok;                // cat_l[l] holds the last forward's concatenation
+  std::vector<const uint16_t*> deep_l;     // the deeper decoder input of level l in that forward
   float* out = nullptr;                    // head output [B][H][W][2] of the last forward
   int lastB = 0;
   // gradient scratch: float32 gradients between layers, one bfloat16
@@ -330,12 +334,21 @@ int cg_net_forward(cg_net* n, const float* input, int32_t B, float* out, void* s
     cgn::launch_conv3(n->a_l[l], cb.cin, cb.wA, n->params + cb.b_off, n->e_l[l], cb.cout, B, h, w, 1, st);
   }
   const uint16_t* deep = n->e_l[L - 1];
+  n->cat_ok.assign(L, 0);
+  n->deep_l.assign(L, nullptr);
   for (int l = L - 2; l >= 0; --l) {
     const int h = hl(n, l), w = wl(n, l);
-    cgn::launch_upcat(deep, ch(n, l + 1), n->e_l[l], ch(n, l), n->cat_l[l], B, h, w, st);
     const Conv& ca = n->conv[li++];
     const Conv& cb = n->conv[li++];
-    cgn::launch_conv3(n->cat_l[l], ca.cin, ca.wA, n->params + ca.b_off, n->da_l[l], ca.cout, B, h, w, 1, st);
+    // the concatenation [up(deep), e_l] is read in place where the row-staged
+    // convolution applies (the backward pass builds it when it needs it)
+    n->deep_l[l] = deep;
+    if (!cgn::launch_conv3_upcat(deep, ch(n, l + 1), n->e_l[l], ch(n, l), ca.wA, n->params + ca.b_off, n->da_l[l],
+                                 ca.cout, B, h, w, 1, st)) {
+      cgn::launch_upcat(deep, ch(n, l + 1), n->e_l[l], ch(n, l), n->cat_l[l], B, h, w, st);
+      n->cat_ok[l] = 1;
+      cgn::launch_conv3(n->cat_l[l], ca.cin, ca.wA, n->params + ca.b_off, n->da_l[l], ca.cout, B, h, w, 1, st);
+    }
     cgn::launch_conv3(n->da_l[l], cb.cin, cb.wA, n->params + cb.b_off, n->d_l[l], cb.cout, B, h, w, 1, st);
     deep = n->d_l[l];
   }
@@ -374,6 +387,10 @@ int cg_net_backward(cg_net* n, const float* target, int32_t B, double* loss, voi
     cgn::launch_conv3_f32(n->GM, cb.cout, cb.wT, n->GB, cb.cin, B, h, w, st);
     // da = relu(conv_a(cat))
     cgn::launch_relu_mask(n->GB, n->da_l[l], n->GM, P * ca.cout, st);
+    if (!n->cat_ok[l]) {   // the forward read it in place
+      cgn::launch_upcat(n->deep_l[l], ch(n, l + 1), n->e_l[l], ch(n, l), n->cat_l[l], B, h, w, st);
+      n->cat_ok[l] = 1;
+    }
     cgn::launch_conv3_wgrad(n->cat_l[l], ca.cin, n->GM, ca.cout, G + ca.w_off, n->part, B, h, w, st);
     cgn::launch_bias_grad(n->GB, n->da_l[l], ca.cout, P, G + ca.b_off, n->part, st);
     cgn::launch_conv3_f32(n->GM, ca.cout, ca.wT, n->GC, ca.cin, B, h, w, st);
